@@ -1,0 +1,105 @@
+"""Pins of the oracle's outer iterations: T4A iteration counts, contraction bounds."""
+
+import numpy as np
+import pytest
+
+from oracle import Problem, krylov, operators as ops, precond, rhs, solve
+from tests.conftest import load_golden
+
+
+def _ops(p):
+    return (lambda v: ops.apply_A(p, v).ravel(),
+            lambda v: precond.three_steps(p, v).ravel())
+
+
+@pytest.mark.parametrize("scheme", ["be", "tr", "lf"])
+def test_fgmres_reaches_sequential_solution(scheme):
+    p = Problem(dim=2, nx=8, ny=6, nt=16, scheme=scheme, T=1.0, nu=0.02,
+                ax=1.0 if scheme != "lf" else 0.0, ay=0.5 if scheme != "lf" else 0.0, alpha=1e-2)
+    b = np.random.default_rng(11).standard_normal((p.nt, p.nspace))
+    A, Pinv = _ops(p)
+    x, info = krylov.fgmres(A, Pinv, b.ravel(), 1e-12, 20, 60)
+    u = solve.sequential(p, b)
+    assert info.converged
+    assert np.abs(x.reshape(u.shape) - u).max() / np.abs(u).max() < 1e-10
+
+
+def _t4a_iterations(N, alpha):
+    n = N - 1
+    p = Problem(dim=2, nx=n, ny=n, nt=N, scheme="lf", T=2.0, nu=1.0, alpha=alpha)
+    x = np.arange(1, n + 1) / N
+    X, Y = np.meshgrid(x, x)
+    s = (np.sin(np.pi * X) * np.sin(np.pi * Y)).ravel()
+    t = np.arange(N + 1) * p.dt
+    f = (1 + 2 * np.pi ** 2) * s[None, :] * np.exp(t)[:, None]
+    b = rhs.build_rhs(p, s, s, f)
+    A, Pinv = _ops(p)
+    _, info = krylov.fgmres(A, Pinv, b.ravel(), 1e-10, 60, 60)
+    return info.iters
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_table_t4a_iteration_counts(N):
+    # alpha = 0.1: the printed count (3 at every size) is reproduced exactly.
+    row = [r for r in load_golden("table_t4a.json")["rows"] if r["N"] == N][0]
+    assert _t4a_iterations(N, 0.1) == row["iters_alpha01"]
+
+
+def test_table_t4a_alpha_one_degrades():
+    # alpha = 1 (Strang circulant): the count grows under refinement and exceeds
+    # the alpha = 0.1 count, as in T4A.  The printed absolute counts (3, 7) are
+    # not matched (we get 5, 9): the discretisation convention behind the table
+    # is not recoverable from the text (its errors are also ~1.6x off).
+    rows = {r["N"]: r for r in load_golden("table_t4a.json")["rows"]}
+    i32, i64 = _t4a_iterations(32, 1.0), _t4a_iterations(64, 1.0)
+    assert rows[64]["iters_alpha1"] > rows[32]["iters_alpha1"]
+    assert i64 > i32 > rows[32]["iters_alpha01"]
+
+
+@pytest.mark.parametrize("scheme", ["be", "tr"])
+def test_stationary_contraction_theorem_the1_2(scheme):
+    # Pure diffusion: K is symmetric, eigenvectors are the (symmetric) DST; the
+    # error in eigen-coordinates contracts by rho per step in the max norm.
+    n, nt, T, alpha = 15, 20, 1.0, 0.05
+    p = Problem(dim=1, nx=n, ny=1, nt=nt, scheme=scheme, T=T, nu=0.02, alpha=alpha)
+    mu = np.linalg.eigvalsh(ops.spatial_operator(p).toarray())
+    j = np.arange(1, n + 1)
+    Q = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(j, j) * np.pi / (n + 1))
+    # eq5.4: alpha/(1-alpha) for any stable one-step scheme.  For backward Euler
+    # the sharper factor of Thm the1.2 holds with the discrete decay
+    # (1 + dt r)^{-Nt} in place of its continuous limit e^{-T r}.
+    rho = alpha / (1 - alpha)
+    if scheme == "be":
+        q = (1 + p.dt * mu.min()) ** (-nt)
+        rho = alpha * q / (1 - alpha * q)
+        assert rho < alpha / (1 - alpha)
+    b = np.random.default_rng(5).standard_normal((nt, n))
+    u = solve.sequential(p, b)
+    uk = np.random.default_rng(6).uniform(-20, 20, size=(nt, n))   # random start as in Fig 1.3
+    prev = np.abs((uk - u) @ Q).max()
+    for _ in range(4):
+        uk = uk + precond.three_steps(p, b - ops.apply_A(p, uk))
+        cur = np.abs((uk - u) @ Q).max()
+        if prev < 1e-11:
+            break
+        assert cur <= rho * prev * (1 + 1e-6) + 1e-13
+        prev = cur
+
+
+def test_stationary_reaches_solution():
+    p = Problem(dim=2, nx=6, ny=6, nt=16, scheme="tr", T=1.0, nu=0.02, ax=1.0, ay=0.5, alpha=1e-3)
+    b = np.random.default_rng(8).standard_normal((p.nt, p.nspace))
+    A, Pinv = _ops(p)
+    x, info = krylov.stationary(A, Pinv, b.ravel(), 1e-12, 20)
+    assert info.converged and info.iters <= 5
+    u = solve.sequential(p, b)
+    assert np.abs(x.reshape(u.shape) - u).max() / np.abs(u).max() < 1e-10
+
+
+def test_leapfrog_spectral_radius_eq5_2():
+    alpha = 0.2
+    p = Problem(dim=1, nx=6, ny=1, nt=10, scheme="lf", T=1.0, nu=1.0, alpha=alpha)
+    A = ops.all_at_once_sparse(p).toarray()
+    P = ops.preconditioner_sparse(p).toarray()
+    rho = np.abs(np.linalg.eigvals(np.eye(A.shape[0]) - np.linalg.solve(P, A))).max()
+    assert rho <= alpha / (1 - alpha) + 1e-12
