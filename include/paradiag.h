@@ -1,0 +1,202 @@
+/*
+ * paradiag.h - C ABI of the ParaDiag-II all-at-once solver for gfx950.
+ *
+ * Problem (Gander, Liu, Wu, Yue, Zhou, "ParaDiag: parallel-in-time algorithms
+ * based on the diagonalization technique", Section 1, eq1.1): solve
+ *
+ *     A u = b,   A = B1 (x) I + B2 (x) K,
+ *
+ * for all Nt time steps at once, where K is the finite-difference spatial
+ * operator of a linear advection-diffusion equation (eq2.2b, homogeneous
+ * Dirichlet data on [0,1]^d, d = 1 or 2) or of the wave equation (eq3.1), and
+ * B1, B2 are the lower-triangular Toeplitz time matrices of backward Euler,
+ * the trapezoidal rule (eq2.5b) or implicit leap-frog (eq3.2b).
+ *
+ * Method: the alpha-circulant preconditioner P_alpha = C1 (x) I + C2 (x) K
+ * (eq1.2, eq2.11b, eq3.4) is applied by the three steps of eq1.3 / eq2.12:
+ * a scaled FFT along time (Step-(a)), independent complex shifted spatial
+ * solves per frequency (Step-(b)) and the inverse scaled FFT (Step-(c)).  It
+ * is used inside flexible GMRES, as a stationary iteration (eq5.1) and as a
+ * one-shot solve; the transposed system A^T lam = g is solved by the same
+ * machinery on time-reversed data with K^T.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  All-at-once vectors are device float64 arrays [batch][nt][ny][nx]
+ *   (x fastest) holding U_1 .. U_Nt.  Spatial fields (U0, u1) are
+ *   [batch][ny][nx]; a source f is [batch][nt+1][ny][nx] sampled at t_0..t_Nt.
+ *   ny = 1 for one space dimension.  Pointers must be 8-byte aligned.
+ * Ownership.  The caller owns every vector and the workspace (device memory
+ *   obtained from any allocator, e.g. PyTorch's).  A plan owns host tables
+ *   only; its device tables live inside the bound workspace.  The library
+ *   allocates no device memory.  A plan is not thread-safe.
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Every
+ *   call is ordered on that stream.  matvec, apply_precond and build_rhs only
+ *   enqueue work; solve and adjoint_solve synchronise the stream once per
+ *   Krylov step and return after `info` is filled.
+ * Aliasing.  Inputs and outputs must not overlap, except apply_precond which
+ *   allows z == r.
+ * Errors.  No C++ exception crosses the ABI.  A negative status means the
+ *   outputs are undefined; paradiag_last_error() returns a message for the
+ *   last non-OK status of the calling thread.
+ */
+#ifndef PARADIAG_H
+#define PARADIAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct paradiag_plan_s* paradiag_plan;
+
+typedef enum {
+  PD_OK = 0,
+  PD_NOT_CONVERGED = 1,     /* outputs valid: best iterate and its residual */
+  PD_ERR_INVALID = -1,      /* bad argument (sizes, alpha outside (0,1], NULL, aliasing) */
+  PD_ERR_UNSUPPORTED = -2,  /* valid problem outside the implemented range */
+  PD_ERR_WORKSPACE = -3,    /* no workspace bound, or too small for the request */
+  PD_ERR_HIP = -4,          /* a HIP runtime call failed */
+  PD_ERR_NONFINITE = -5,    /* NaN/Inf in the right-hand side or in Krylov scalars */
+  PD_ERR_BREAKDOWN = -6     /* singular pivot in setup or a Krylov breakdown */
+} paradiag_status;
+
+typedef enum { PD_BE = 0, PD_TR = 1, PD_LEAPFROG = 2 } paradiag_scheme;
+
+/* Arithmetic of the preconditioner.  The all-at-once residual, the matvec,
+ * the Krylov vectors, the Arnoldi process and the alpha-scaling tables are
+ * float64 in every mode. */
+typedef enum {
+  PD_PREC_FP64 = 0,           /* FFT, x-transform and line solves in float64 */
+  PD_PREC_FP32 = 1,           /* FFT, x-transform and line solves in float32 */
+  PD_PREC_FP32_BF16GEMM = 2   /* as FP32, x-transform on bf16 MFMA with fp32 accumulation */
+} paradiag_prec;
+
+typedef enum {
+  PD_MODE_FGMRES = 0,      /* flexible GMRES(restart) preconditioned by P_alpha */
+  PD_MODE_STATIONARY = 1,  /* u <- u + P_alpha^{-1}(b - A u)  (eq5.1) */
+  PD_MODE_DIRECT = 2       /* u = P_alpha^{-1} b once (solution of the alpha-circulant system) */
+} paradiag_mode;
+
+typedef struct {
+  int32_t dim;        /* 1 or 2 */
+  int32_t nx, ny;     /* interior points per direction; ny = 1 when dim = 1; nx, ny in [1, 4096] */
+  int32_t nt;         /* time steps: a power of two in [4, 4096] */
+  int32_t batch;      /* independent right-hand sides, 1..64 */
+  int32_t scheme;     /* paradiag_scheme */
+  int32_t prec;       /* paradiag_prec */
+  int32_t reserved;   /* must be 0 */
+  double T;           /* final time; dt = T / nt */
+  double nu;          /* diffusion coefficient (c^2 for the wave equation), > 0 */
+  double ax, ay;      /* velocity (0 for the wave equation); |a| h / (2 nu) < 1 required */
+  double alpha;       /* alpha-circulant parameter in (0, 1] */
+} paradiag_problem;
+
+typedef struct {
+  int32_t mode;       /* paradiag_mode */
+  int32_t restart;    /* FGMRES cycle length m, 1..64 (ignored otherwise) */
+  int32_t max_iter;   /* total preconditioner applications allowed, >= 1 */
+  int32_t use_x0;     /* 1: u holds the initial guess on entry; 0: start from zero */
+  double rtol;        /* target ||b - A u||_2 / ||b||_2 per right-hand side, > 0 */
+} paradiag_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* preconditioner applications performed */
+  int32_t converged;      /* 1 if every right-hand side met rtol */
+  double rel_resid;       /* max over the batch of the final true relative residual */
+  int32_t* iters_per_rhs; /* optional, caller-owned arrays of length batch (may be NULL) */
+  double* resid_per_rhs;
+  double* history;        /* optional caller-owned array: max relative residual estimate per step */
+  int32_t history_cap;    /* capacity of history */
+  int32_t history_len;    /* entries written */
+} paradiag_solve_info;
+
+/* Validate the problem and build host tables: the time symbols
+ * lambda_j = fft(Gamma_alpha c_j) of Lemma 1, the Gamma_alpha table
+ * (alpha^{n/Nt}), FFT twiddles, and the x-direction basis of K_x: the sine
+ * basis when K_x is symmetric, otherwise a unitary complex Schur form
+ * K_x = Q T Q^H computed on the host in float64.  Host only: no device call.
+ * Returns PD_ERR_INVALID / PD_ERR_UNSUPPORTED for a problem outside the
+ * stated ranges; *out is NULL then. */
+paradiag_status paradiag_setup(const paradiag_problem* prob, paradiag_plan* out);
+
+/* Bytes of device workspace needed for calls with `opts` (opts may be NULL:
+ * enough for matvec, apply_precond, build_rhs and PD_MODE_DIRECT).  Host only. */
+paradiag_status paradiag_workspace_size(paradiag_plan plan, const paradiag_solve_opts* opts,
+                                        size_t* bytes);
+
+/* Hand the plan a device workspace of `bytes` bytes (256-byte aligned) and
+ * upload the device tables into it on `stream`.  The caller keeps ownership
+ * and must keep it alive until the plan is destroyed or rebound. */
+paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, size_t bytes,
+                                        void* stream);
+
+/* b = all-at-once right-hand side from U0, the initial velocity u1 (leap-frog
+ * only; NULL = 0) and the source f (NULL = 0).  theta-method: b_1 =
+ * (I/dt - (1-theta)K)U0 + theta f_1 + (1-theta) f_0, b_n = theta f_n +
+ * (1-theta) f_{n-1} (eq2.5 with a source); leap-frog: first two rows from
+ * the scheme at t_0 with a central ghost value (eq3.2). */
+paradiag_status paradiag_build_rhs(paradiag_plan plan, const double* U0, const double* u1,
+                                   const double* f, double* b, void* stream);
+
+/* Transpose of the map (U0, u1, f) -> b applied to lam [batch][nt][ny][nx]:
+ * gU0 [batch][ny][nx], gu1 [batch][ny][nx] (may be NULL), gf
+ * [batch][nt+1][ny][nx] (may be NULL).  Used for gradients. */
+paradiag_status paradiag_rhs_transpose(paradiag_plan plan, const double* lam, double* gU0,
+                                       double* gu1, double* gf, void* stream);
+
+/* y = A u (eq1.1), float64.  transpose != 0 gives y = A^T u. */
+paradiag_status paradiag_matvec(paradiag_plan plan, const double* u, double* y, int32_t transpose,
+                                void* stream);
+
+/* z = P_alpha^{-1} r by Step-(a), (b), (c) of eq2.12, in the plan's
+ * preconditioner precision (input and output float64).  z == r allowed. */
+paradiag_status paradiag_apply_precond(paradiag_plan plan, const double* r, double* z,
+                                       void* stream);
+
+/* Solve A u = b per opts->mode.  u: in = initial guess if opts->use_x0,
+ * out = solution.  Returns PD_NOT_CONVERGED (u = last iterate) when max_iter
+ * is reached first. */
+paradiag_status paradiag_solve(paradiag_plan plan, const double* b, double* u,
+                               const paradiag_solve_opts* opts, paradiag_solve_info* info,
+                               void* stream);
+
+/* Solve A^T lam = g.  Uses A^T = (J (x) I)(B1 (x) I + B2 (x) K^T)(J (x) I) with J
+ * the time reversal (Toeplitz and alpha-circulant matrices are persymmetric),
+ * so the same preconditioned iteration runs on reversed data with K^T. */
+paradiag_status paradiag_adjoint_solve(paradiag_plan plan, const double* g, double* lam,
+                                       const paradiag_solve_opts* opts,
+                                       paradiag_solve_info* info, void* stream);
+
+/* Copy the host x-basis of the plan: q and t receive nx*nx complex float64
+ * values (interleaved re, im; row-major) with K_x = Q T Q^H (adjoint != 0:
+ * the basis of K_x^T).  Host only; for inspection and tests. */
+paradiag_status paradiag_get_xbasis(paradiag_plan plan, int32_t adjoint, double* q, double* t);
+
+/* Copy the host time symbols lambda_1, lambda_2 for n = 0..nt/2 (interleaved
+ * complex float64, nt/2+1 values each).  Host only. */
+paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* lam2);
+
+/* Stage timing.  When enabled, every later call records HIP events around
+ * each kernel launch on the call's stream; paradiag_get_stage_times returns,
+ * per stage (see PD_STAGE_*), the summed milliseconds and launch counts since
+ * the last reset (it synchronises on the recorded events). */
+enum {
+  PD_STAGE_FFT_FWD = 0, PD_STAGE_XFORM_FWD = 1, PD_STAGE_LINE_SOLVE = 2, PD_STAGE_XFORM_INV = 3,
+  PD_STAGE_FFT_INV = 4, PD_STAGE_MATVEC = 5, PD_STAGE_ORTHO = 6, PD_STAGE_OTHER = 7,
+  PD_NUM_STAGES = 8
+};
+paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable);
+paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,
+                                         int32_t reset);
+
+void paradiag_destroy(paradiag_plan plan);
+const char* paradiag_last_error(void);
+const char* paradiag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARADIAG_H */

@@ -1,0 +1,849 @@
+// C ABI of the ParaDiag-II library: plan setup (host tables), workspace
+// binding, and the drivers of the three solve modes.  See include/paradiag.h.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace pd {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr int MAXV = 33;   // Krylov slots per right-hand side (restart <= 32)
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t compute_elem_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+size_t spec_elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ tables
+
+namespace {
+
+void time_columns(int scheme, double dt, double* c1, double* c2, int* L, double* theta) {
+  c1[0] = c1[1] = c1[2] = 0;
+  c2[0] = c2[1] = c2[2] = 0;
+  if (scheme == PD_LEAPFROG) {
+    // implicit leap-frog (eq3.2b): B1 = tridiag-Toeplitz (1,-2,1)/dt^2, B2 = (1/2, 0, 1/2)
+    c1[0] = 1.0 / (dt * dt); c1[1] = -2.0 / (dt * dt); c1[2] = 1.0 / (dt * dt);
+    c2[0] = 0.5; c2[1] = 0.0; c2[2] = 0.5;
+    *L = 3;
+    *theta = 0.5;
+  } else {
+    // theta-method with uniform step (eq2.5b): B1 = (1, -1)/dt, B2 = (theta, 1 - theta)
+    double th = (scheme == PD_BE) ? 1.0 : 0.5;
+    c1[0] = 1.0 / dt; c1[1] = -1.0 / dt;
+    c2[0] = th; c2[1] = 1.0 - th;
+    *L = 2;
+    *theta = th;
+  }
+}
+
+// 1D factor -nu d2 + a d on n Dirichlet points: tridiag(lo, di, up)
+void factor_1d(int n, double nu, double a, double* lo, double* di, double* up) {
+  double h = 1.0 / (n + 1);
+  *lo = -nu / (h * h) - a / (2 * h);
+  *di = 2 * nu / (h * h);
+  *up = -nu / (h * h) + a / (2 * h);
+}
+
+}  // namespace
+
+static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
+  out = nullptr;
+  if (!pr) { set_error("problem is NULL"); return PD_ERR_INVALID; }
+  const paradiag_problem& p = *pr;
+  if (p.dim != 1 && p.dim != 2) { set_error("dim must be 1 or 2"); return PD_ERR_INVALID; }
+  if (p.nx < 1 || p.ny < 1 || p.nt < 1 || p.batch < 1) { set_error("sizes must be positive"); return PD_ERR_INVALID; }
+  if (p.dim == 1 && p.ny != 1) { set_error("ny must be 1 in one dimension"); return PD_ERR_INVALID; }
+  if (p.batch > 64) { set_error("batch must be <= 64"); return PD_ERR_INVALID; }
+  if (!(p.alpha > 0.0 && p.alpha <= 1.0)) { set_error("alpha must lie in (0, 1]"); return PD_ERR_INVALID; }
+  if (!(p.T > 0.0) || !(p.nu > 0.0) || !std::isfinite(p.T) || !std::isfinite(p.nu) ||
+      !std::isfinite(p.ax) || !std::isfinite(p.ay)) {
+    set_error("T and nu must be positive and finite"); return PD_ERR_INVALID;
+  }
+  if (p.scheme < 0 || p.scheme > 2) { set_error("unknown scheme"); return PD_ERR_INVALID; }
+  if (p.prec < 0 || p.prec > 2) { set_error("unknown precision"); return PD_ERR_INVALID; }
+  if (p.reserved != 0) { set_error("reserved must be 0"); return PD_ERR_INVALID; }
+  if (!is_pow2(p.nt) || p.nt < 4 || p.nt > 4096) {
+    set_error("nt must be a power of two in [4, 4096]"); return PD_ERR_UNSUPPORTED;
+  }
+  if (p.dim == 1 && p.nx > 2048) { set_error("nx > 2048 unsupported in 1D"); return PD_ERR_UNSUPPORTED; }
+  if (p.dim == 2 && (p.ny > 2048 || p.nx > 2048)) { set_error("nx, ny > 2048 unsupported"); return PD_ERR_UNSUPPORTED; }
+  if (p.dim == 2 && p.ax != 0.0 && p.nx > 1024) {
+    set_error("non-symmetric x factor with nx > 1024 unsupported (host Schur cost)"); return PD_ERR_UNSUPPORTED;
+  }
+  double hx = 1.0 / (p.nx + 1), hy = 1.0 / (p.ny + 1);
+  if (std::fabs(p.ax) * hx / (2 * p.nu) >= 1.0 || (p.dim == 2 && std::fabs(p.ay) * hy / (2 * p.nu) >= 1.0)) {
+    set_error("cell Peclet number |a| h / (2 nu) must be < 1"); return PD_ERR_UNSUPPORTED;
+  }
+
+  std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
+  if (!pl) { set_error("out of host memory"); return PD_ERR_INVALID; }
+  pl->p = p;
+  pl->prec = static_cast<Prec>(p.prec);
+  Geom& g = pl->g;
+  g.B = p.batch; g.nt = p.nt; g.F = p.nt / 2 + 1;
+  g.nx = p.nx; g.ny = p.ny;
+  if (p.dim == 2) { g.sx = p.nx; g.sy = p.ny; } else { g.sx = 1; g.sy = p.nx; }
+  g.S = (int64_t)p.nx * p.ny;
+  g.N1 = g.S * p.nt;
+  g.NA = g.N1 * p.batch;
+  g.spec_elems = (int64_t)g.B * g.F * g.sy * 2 * g.sx;
+
+  const double dt = p.T / p.nt;
+  time_columns(p.scheme, dt, pl->c1, pl->c2, &pl->L, &pl->theta);
+
+  // time symbols lambda_j(n) = sum_k c_jk z_n^k, z_n = alpha^{1/Nt} e^{-2 pi i n/Nt}
+  // (the Fourier transform of Gamma_alpha c_j, Lemma 1)
+  const double PI = 3.14159265358979323846;
+  double r = std::pow(p.alpha, 1.0 / p.nt);
+  pl->lam1.resize(g.F);
+  pl->lam2.resize(g.F);
+  for (int n = 0; n < g.F; ++n) {
+    double ang = -2.0 * PI * n / p.nt;
+    cd z = std::polar(r, ang), zk = 1.0, s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < pl->L; ++k) {
+      s1 += pl->c1[k] * zk;
+      s2 += pl->c2[k] * zk;
+      zk *= z;
+    }
+    pl->lam1[n] = s1;
+    pl->lam2[n] = s2;
+  }
+  pl->gam.resize(p.nt);
+  pl->invgam.resize(p.nt);
+  double la = std::log(p.alpha);
+  for (int n = 0; n < p.nt; ++n) {
+    pl->gam[n] = std::exp(la * n / p.nt);
+    pl->invgam[n] = std::exp(-la * n / p.nt) / p.nt;
+  }
+
+  // spatial operator and its transpose
+  double lx, dx, ux, ly = 0, dy = 0, uy = 0;
+  factor_1d(p.nx, p.nu, p.ax, &lx, &dx, &ux);
+  if (p.dim == 2) factor_1d(p.ny, p.nu, p.ay, &ly, &dy, &uy);
+  for (int v = 0; v < 2; ++v) {
+    SpaceOp& op = pl->op[v];
+    double lxv = v ? ux : lx, uxv = v ? lx : ux, lyv = v ? uy : ly, uyv = v ? ly : uy;
+    op.sxl = lxv; op.sxu = uxv; op.syl = lyv; op.syu = uyv; op.sd = dx + dy;
+    if (p.dim == 1) { op.lo = lxv; op.di = dx; op.up = uxv; }
+    else { op.lo = lyv; op.di = dy; op.up = uyv; }
+  }
+  if (p.dim == 2) {
+    const int n = p.nx;
+    pl->schur = (p.ax != 0.0);
+    std::vector<cd> Q((size_t)n * n), T((size_t)n * n, cd(0.0));
+    if (!pl->schur) {
+      // symmetric factor: sine basis, eigenvalues di + 2 lo cos(k pi/(n+1))
+      double s = std::sqrt(2.0 / (n + 1));
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) Q[(size_t)j * n + k] = s * std::sin((j + 1.0) * (k + 1.0) * PI / (n + 1));
+      for (int k = 0; k < n; ++k) T[(size_t)k * n + k] = dx + 2 * lx * std::cos((k + 1.0) * PI / (n + 1));
+    } else {
+      std::vector<cd> H((size_t)n * n, cd(0.0));
+      for (int i = 0; i < n; ++i) {
+        H[(size_t)i * n + i] = dx;
+        if (i > 0) H[(size_t)i * n + i - 1] = lx;
+        if (i + 1 < n) H[(size_t)i * n + i + 1] = ux;
+      }
+      if (!complex_schur(n, H, Q)) { set_error("Schur iteration did not converge"); return PD_ERR_BREAKDOWN; }
+      T = H;
+    }
+    pl->op[0].Q = Q;
+    pl->op[0].Tm = T;
+    // K_x^T = conj(Q) T^T Q^T = (conj(Q) J)(J T^T J)(J Q^T): Schur form of the transpose
+    std::vector<cd> Qa((size_t)n * n), Ta((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        Qa[(size_t)i * n + k] = std::conj(Q[(size_t)i * n + (n - 1 - k)]);
+        Ta[(size_t)i * n + k] = T[(size_t)(n - 1 - k) * n + (n - 1 - i)];
+      }
+    if (!pl->schur) { Qa = Q; Ta = T; }
+    pl->op[1].Q = Qa;
+    pl->op[1].Tm = Ta;
+  }
+  out = pl.release();
+  return PD_OK;
+}
+
+size_t tables_bytes(const Plan& pl) {
+  const Geom& g = pl.g;
+  size_t b = 0;
+  b += align_up(sizeof(double) * g.nt) * 2;          // gam, invgam
+  b += align_up(sizeof(double2) * g.nt);              // twiddles f64
+  b += align_up(sizeof(float2) * g.nt);               // twiddles f32
+  b += align_up(sizeof(double2) * 2 * g.F);           // lam
+  if (pl.p.dim == 2) {
+    const size_t n = g.nx;
+    size_t gm = pl.schur ? (2 * n) * (2 * n) : n * n;
+    for (int v = 0; v < 2; ++v) {
+      b += align_up(sizeof(double2) * n);                             // tk
+      b += 2 * align_up(gm * compute_elem_bytes(pl.prec));            // g_fwd, g_inv
+      if (pl.schur) b += align_up(2 * n * n * spec_elem_bytes(pl.prec));  // T (line precision)
+    }
+  }
+  b += 2 * align_up((size_t)g.spec_elems * spec_elem_bytes(pl.prec));
+  return b;
+}
+
+size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o) {
+  if (!o) return 0;
+  const Geom& g = pl.g;
+  size_t small = align_up(sizeof(double) * g.B * (size_t)2048 * MAXV) + 8 * align_up(sizeof(double) * g.B * MAXV);
+  size_t zb = (pl.prec == Prec::F64) ? 8 : 4;
+  if (o->mode == PD_MODE_FGMRES) {
+    int m = std::max(1, std::min(o->restart, 32));
+    return small + align_up(sizeof(double) * (size_t)g.NA) * (m + 1) + align_up(zb * (size_t)g.NA) * m;
+  }
+  // stationary: the residual vector; direct: the residual it reports
+  return small + align_up(sizeof(double) * (size_t)g.NA);
+}
+
+// ------------------------------------------------------------------ timing
+
+struct Timed {
+  Plan& pl;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(Plan& p, int st, hipStream_t str) : pl(p), stage(st), s(str) {
+    if (!pl.timer.enabled) return;
+    a = take();
+    b = take();
+    hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    if (!pl.timer.pool.empty()) { hipEvent_t e = pl.timer.pool.back(); pl.timer.pool.pop_back(); return e; }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  ~Timed() {
+    if (!pl.timer.enabled) return;
+    hipEventRecord(b, s);
+    pl.timer.pending.push_back({stage, a, b});
+  }
+};
+
+static void drain_timer(Plan& pl) {
+  for (auto& r : pl.timer.pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    pl.timer.ms[r.stage] += ms;
+    pl.timer.count[r.stage] += 1;
+    pl.timer.pool.push_back(r.a);
+    pl.timer.pool.push_back(r.b);
+  }
+  pl.timer.pending.clear();
+}
+
+// ------------------------------------------------------------ operations
+
+static void apply_prec(Plan& pl, int variant, const double* in, const double* bscale, void* out,
+                       bool out_f32, int accumulate, hipStream_t s) {
+  const SpaceOp& op = pl.op[variant];
+  { Timed t(pl, PD_STAGE_FFT_FWD, s); fft_time_forward(pl, in, bscale, pl.spec_a, variant, s); }
+  if (pl.p.dim == 2) {
+    { Timed t(pl, PD_STAGE_XFORM_FWD, s); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
+    {
+      Timed t(pl, PD_STAGE_LINE_SOLVE, s);
+      if (pl.schur) schur_sweep(pl, op, pl.spec_b, s);
+      else line_solve(pl, op, pl.spec_b, s);
+    }
+    { Timed t(pl, PD_STAGE_XFORM_INV, s); xform(pl, op, false, pl.spec_b, pl.spec_a, s); }
+  } else {
+    Timed t(pl, PD_STAGE_LINE_SOLVE, s);
+    line_solve(pl, op, pl.spec_a, s);
+  }
+  { Timed t(pl, PD_STAGE_FFT_INV, s); fft_time_inverse(pl, pl.spec_a, out, out_f32, accumulate, variant, s); }
+}
+
+static void apply_A(Plan& pl, int variant, const void* u, bool u_f32, const double* b, double* y,
+                    hipStream_t s) {
+  Timed t(pl, PD_STAGE_MATVEC, s);
+  matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s);
+}
+
+namespace {
+
+struct Small {
+  double* partial;
+  double* h1;
+  double* c1;
+  double* h2;
+  double* c2;
+  double* sigma;
+  double* y;
+  double* nrm;
+};
+
+Small carve_small(Plan& pl, char*& p) {
+  const Geom& g = pl.g;
+  Small sm;
+  sm.partial = (double*)p; p += align_up(sizeof(double) * g.B * (size_t)2048 * MAXV);
+  double** slots[] = {&sm.h1, &sm.c1, &sm.h2, &sm.c2, &sm.sigma, &sm.y, &sm.nrm};
+  for (double** q : slots) { *q = (double*)p; p += align_up(sizeof(double) * g.B * MAXV); }
+  p += align_up(sizeof(double) * g.B * MAXV);
+  return sm;
+}
+
+// Reduction kernels take sigma per slot; slots >= nscale use 1.  We keep a
+// device vector of ones at the tail of sigma for that purpose by launching the
+// reduction with sigma == nullptr for unscaled sums.
+void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s) {
+  multi_dot(pl, v, 0, 1, v, sm.partial, s);
+  reduce_partials(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s);
+  std::vector<double> tmp((size_t)pl.g.B * MAXV);
+  hipMemcpyAsync(tmp.data(), sm.nrm, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost, s);
+  hipStreamSynchronize(s);
+  out.resize(pl.g.B);
+  // |.| keeps a NaN visible (std::max(0, NaN) would hide it)
+  for (int b = 0; b < pl.g.B; ++b) out[b] = std::sqrt(std::fabs(tmp[(size_t)b * MAXV]));
+}
+
+}  // namespace
+
+
+static paradiag_status check_hip(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PD_ERR_HIP;
+  }
+  return PD_OK;
+}
+
+static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double* u,
+                                  const paradiag_solve_opts* o, paradiag_solve_info* info,
+                                  hipStream_t s) {
+  const Geom& g = pl.g;
+  const int B = g.B;
+  char* p = pl.solver_base;
+  size_t need = solver_bytes(pl, o);
+  if ((size_t)(pl.ws + pl.ws_bytes - pl.solver_base) < need) {
+    set_error("workspace too small for this solve (see paradiag_workspace_size)");
+    return PD_ERR_WORKSPACE;
+  }
+  const bool zf32 = pl.prec != Prec::F64;
+  const size_t zb = zf32 ? 4 : 8;
+  Small sm = carve_small(pl, p);
+  std::vector<double> bn;
+  { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, b, sm, bn, s); }
+  for (int i = 0; i < B; ++i)
+    if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
+  std::vector<int> it_rhs(B, 0);
+  std::vector<double> res(B, 0.0);
+  int iters = 0;
+  int hist_len = 0;
+  auto push_hist = [&](double v) {
+    if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
+    ++hist_len;
+  };
+  auto finish = [&](bool conv) -> paradiag_status {
+    double mx = 0;
+    for (int i = 0; i < B; ++i) mx = std::max(mx, res[i]);
+    if (info) {
+      info->iters = iters;
+      info->converged = conv ? 1 : 0;
+      info->rel_resid = mx;
+      info->history_len = std::min(hist_len, info->history ? info->history_cap : 0);
+      for (int i = 0; i < B; ++i) {
+        if (info->iters_per_rhs) info->iters_per_rhs[i] = it_rhs[i];
+        if (info->resid_per_rhs) info->resid_per_rhs[i] = res[i];
+      }
+    }
+    paradiag_status st = check_hip("solve");
+    if (st != PD_OK) return st;
+    return conv ? PD_OK : PD_NOT_CONVERGED;
+  };
+  auto rel = [&](const std::vector<double>& nr) {
+    bool all = true;
+    for (int i = 0; i < B; ++i) {
+      res[i] = bn[i] > 0 ? nr[i] / bn[i] : 0.0;
+      if (res[i] > o->rtol) all = false;
+    }
+    return all;
+  };
+
+  if (o->mode == PD_MODE_DIRECT) {
+    apply_prec(pl, variant, b, nullptr, u, false, 0, s);
+    iters = 1;
+    for (int i = 0; i < B; ++i) it_rhs[i] = 1;
+    // residual of the result with respect to A (reported, not iterated)
+    std::vector<double> nr;
+    double* rv = (double*)p;
+    apply_A(pl, variant, u, false, b, rv, s);
+    { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, rv, sm, nr, s); }
+    rel(nr);
+    push_hist(*std::max_element(res.begin(), res.end()));
+    return finish(true);
+  }
+
+  if (o->mode == PD_MODE_STATIONARY) {
+    double* r = (double*)p;
+    if (!o->use_x0) fill_zero(u, g.NA, s);
+    std::vector<double> nr;
+    while (true) {
+      apply_A(pl, variant, u, false, b, r, s);
+      { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, r, sm, nr, s); }
+      bool all = rel(nr);
+      for (int i = 0; i < B; ++i)
+        if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
+      push_hist(*std::max_element(res.begin(), res.end()));
+      if (all) return finish(true);
+      if (iters >= o->max_iter) return finish(false);
+      apply_prec(pl, variant, r, nullptr, u, false, 1, s);
+      ++iters;
+      for (int i = 0; i < B; ++i)
+        if (res[i] > o->rtol) it_rhs[i] = iters;
+    }
+  }
+
+  // ---------------------------------------------------------------- FGMRES
+  const int m = std::max(1, std::min(o->restart, 32));
+  double* V = (double*)p;
+  const int64_t vs = (int64_t)(align_up(sizeof(double) * (size_t)g.NA) / sizeof(double));
+  p += align_up(sizeof(double) * (size_t)g.NA) * (m + 1);
+  char* Z = p;
+  const int64_t zs = (int64_t)(align_up(zb * (size_t)g.NA) / zb);
+  auto Vj = [&](int j) { return V + (int64_t)j * vs; };
+  auto Zj = [&](int j) { return (void*)(Z + (size_t)j * zs * zb); };
+
+  if (!o->use_x0) fill_zero(u, g.NA, s);
+  std::vector<double> H((size_t)B * (m + 1) * m), gv((size_t)B * (m + 1)), cs((size_t)B * m),
+      sn((size_t)B * m), sig((size_t)B * MAXV), hbuf((size_t)B * MAXV * 5), yv((size_t)B * MAXV);
+  std::vector<double> nr, bs(B);   // host staging buffers live across async copies
+  bool first = true;
+  while (true) {
+    // residual of the current iterate into V_0
+    if (first && !o->use_x0) copy_vec(b, Vj(0), g.NA, s);
+    else apply_A(pl, variant, u, false, b, Vj(0), s);
+    first = false;
+    { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, Vj(0), sm, nr, s); }
+    bool all = rel(nr);
+    for (int i = 0; i < B; ++i)
+      if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
+    push_hist(*std::max_element(res.begin(), res.end()));
+    if (all) return finish(true);
+    if (iters >= o->max_iter) return finish(false);
+    std::vector<char> active(B);
+    for (int i = 0; i < B; ++i) active[i] = res[i] > o->rtol && nr[i] > 0;
+    std::fill(sig.begin(), sig.end(), 0.0);
+    for (int i = 0; i < B; ++i) {
+      if (active[i]) sig[(size_t)i * MAXV] = 1.0 / nr[i];
+      gv[(size_t)i * (m + 1)] = nr[i];
+    }
+    hipMemcpyAsync(sm.sigma, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, s);
+    std::vector<int> kk(B, 0);   // columns used per right-hand side
+    std::vector<char> live = active;
+    int j = 0;
+    for (; j < m; ++j) {
+      // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a))
+      for (int i = 0; i < B; ++i) bs[i] = sig[(size_t)i * MAXV + j];
+      hipMemcpyAsync(sm.y, bs.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+      apply_prec(pl, variant, Vj(j), sm.y, Zj(j), zf32, 0, s);
+      apply_A(pl, variant, Zj(j), zf32, nullptr, Vj(j + 1), s);
+      {
+        Timed t(pl, PD_STAGE_ORTHO, s);
+        double* w = Vj(j + 1);
+        // classical Gram-Schmidt, two passes; the second pass's dots come from the
+        // first pass's update kernel, the final norm by Pythagoras
+        multi_dot(pl, V, vs, j + 1, w, sm.partial, s);
+        reduce_partials(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
+        update_dot(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
+        reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
+        update_dot(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
+        hipMemcpyAsync(hbuf.data(), sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hbuf.data() + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
+                       hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+      }
+      ++iters;
+      double est_max = 0;
+      bool any_live = false;
+      for (int i = 0; i < B; ++i) {
+        const double* h1 = hbuf.data() + (size_t)i * MAXV;
+        const double* h2 = hbuf.data() + (size_t)B * MAXV + (size_t)i * MAXV;
+        double* Hc = H.data() + (size_t)i * (m + 1) * m;   // column-major (m+1) x m
+        for (int q = 0; q <= j; ++q) {
+          double v = h1[q] + h2[q];
+          if (!std::isfinite(v)) { set_error("non-finite Krylov scalar"); return PD_ERR_NONFINITE; }
+          Hc[(size_t)j * (m + 1) + q] = v;
+        }
+        double nn = h2[j + 1];
+        for (int q = 0; q <= j; ++q) nn -= h2[q] * h2[q];
+        double hn = nn > 0 ? std::sqrt(nn) : 0.0;
+        Hc[(size_t)j * (m + 1) + j + 1] = hn;
+        if (!live[i]) { sig[(size_t)i * MAXV + j + 1] = 0.0; continue; }
+        // Givens rotations
+        double* col = Hc + (size_t)j * (m + 1);
+        double* c_ = cs.data() + (size_t)i * m;
+        double* s_ = sn.data() + (size_t)i * m;
+        double* gg = gv.data() + (size_t)i * (m + 1);
+        for (int q = 0; q < j; ++q) {
+          double t = c_[q] * col[q] + s_[q] * col[q + 1];
+          col[q + 1] = -s_[q] * col[q] + c_[q] * col[q + 1];
+          col[q] = t;
+        }
+        double a = col[j], bb = col[j + 1];
+        double cc = 1, ss = 0;
+        if (bb != 0.0) { double rr = std::hypot(a, bb); cc = a / rr; ss = bb / rr; }
+        c_[j] = cc; s_[j] = ss;
+        col[j] = cc * a + ss * bb;
+        col[j + 1] = 0.0;
+        gg[j + 1] = -ss * gg[j];
+        gg[j] = cc * gg[j];
+        kk[i] = j + 1;
+        it_rhs[i] += 1;
+        double est = std::fabs(gg[j + 1]) / bn[i];
+        est_max = std::max(est_max, est);
+        if (est <= o->rtol || hn == 0.0) live[i] = 0;
+        else any_live = true;
+        sig[(size_t)i * MAXV + j + 1] = (hn > 0 && live[i]) ? 1.0 / hn : 0.0;
+      }
+      push_hist(est_max);
+      if (!any_live || iters >= o->max_iter || j + 1 == m) { ++j; break; }
+      hipMemcpyAsync(sm.sigma, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, s);
+    }
+    // solve the triangular systems and update x
+    std::fill(yv.begin(), yv.end(), 0.0);
+    int kmax = 0;
+    for (int i = 0; i < B; ++i) {
+      int k = kk[i];
+      kmax = std::max(kmax, k);
+      const double* Hc = H.data() + (size_t)i * (m + 1) * m;
+      const double* gg = gv.data() + (size_t)i * (m + 1);
+      double* y = yv.data() + (size_t)i * MAXV;
+      for (int q = k - 1; q >= 0; --q) {
+        double acc = gg[q];
+        for (int c = q + 1; c < k; ++c) acc -= Hc[(size_t)c * (m + 1) + q] * y[c];
+        double d = Hc[(size_t)q * (m + 1) + q];
+        y[q] = d != 0.0 ? acc / d : 0.0;
+      }
+    }
+    if (kmax > 0) {
+      hipMemcpyAsync(sm.y, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s);
+      Timed t(pl, PD_STAGE_OTHER, s);
+      x_update(pl, Z, zf32, zs, kmax, sm.y, u, s);
+    }
+  }
+}
+
+}  // namespace pd
+
+// ====================================================================== ABI
+
+using namespace pd;
+
+// bf16 storage: float rounded to nearest even, upper 16 bits kept
+struct Bf16Bits { uint16_t v; };
+static uint16_t to_bf16_bits(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+static void store_compute(void* dst, const std::vector<double>& v, hipStream_t s,
+                          std::vector<std::vector<char>>& keep) {
+  std::vector<char> buf(v.size() * sizeof(T));
+  T* t = reinterpret_cast<T*>(buf.data());
+  for (size_t i = 0; i < v.size(); ++i) {
+    if constexpr (std::is_same<T, Bf16Bits>::value) t[i].v = to_bf16_bits(v[i]);
+    else t[i] = (T)v[i];
+  }
+  hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+  keep.push_back(std::move(buf));
+}
+
+extern "C" {
+
+const char* paradiag_last_error(void) { return g_last_error.c_str(); }
+const char* paradiag_version(void) { return "paradiag-gfx950 0.1"; }
+
+paradiag_status paradiag_setup(const paradiag_problem* prob, paradiag_plan* out) {
+  if (!out) { set_error("out is NULL"); return PD_ERR_INVALID; }
+  *out = nullptr;
+  try {
+    Plan* pl = nullptr;
+    paradiag_status st = build_plan(prob, pl);
+    if (st != PD_OK) return st;
+    *out = reinterpret_cast<paradiag_plan>(pl);
+    return PD_OK;
+  } catch (...) {
+    set_error("setup failed (host allocation)");
+    return PD_ERR_INVALID;
+  }
+}
+
+void paradiag_destroy(paradiag_plan plan) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl) return;
+  for (auto& r : pl->timer.pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+  for (auto e : pl->timer.pool) hipEventDestroy(e);
+  delete pl;
+}
+
+paradiag_status paradiag_workspace_size(paradiag_plan plan, const paradiag_solve_opts* opts,
+                                        size_t* bytes) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl || !bytes) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (opts && (opts->mode < 0 || opts->mode > 2)) { set_error("unknown mode"); return PD_ERR_INVALID; }
+  *bytes = tables_bytes(*pl) + solver_bytes(*pl, opts);
+  return PD_OK;
+}
+
+
+
+paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, size_t bytes,
+                                        void* stream) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl || !workspace) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) { set_error("workspace must be 256-byte aligned"); return PD_ERR_INVALID; }
+  size_t need = tables_bytes(*pl);
+  if (bytes < need) { set_error("workspace smaller than the device tables"); return PD_ERR_WORKSPACE; }
+  hipStream_t s = (hipStream_t)stream;
+  const Geom& g = pl->g;
+  char* p = (char*)workspace;
+  auto take = [&](size_t n) { char* r = p; p += align_up(n); return r; };
+  std::vector<std::vector<char>> keep;
+  auto up = [&](void* dst, const void* src, size_t n) {
+    std::vector<char> buf((const char*)src, (const char*)src + n);
+    hipMemcpyAsync(dst, buf.data(), n, hipMemcpyHostToDevice, s);
+    keep.push_back(std::move(buf));
+  };
+  pl->d_gam = (double*)take(sizeof(double) * g.nt);
+  pl->d_invgam = (double*)take(sizeof(double) * g.nt);
+  pl->d_tw64 = (double2*)take(sizeof(double2) * g.nt);
+  pl->d_tw32 = (float2*)take(sizeof(float2) * g.nt);
+  pl->d_lam = (double2*)take(sizeof(double2) * 2 * g.F);
+  up(pl->d_gam, pl->gam.data(), sizeof(double) * g.nt);
+  up(pl->d_invgam, pl->invgam.data(), sizeof(double) * g.nt);
+  {
+    const double PI = 3.14159265358979323846;
+    std::vector<double2> t64(g.nt);
+    std::vector<float2> t32(g.nt);
+    for (int k = 0; k < g.nt; ++k) {
+      double a = -2.0 * PI * k / g.nt;
+      t64[k] = double2{std::cos(a), std::sin(a)};
+      t32[k] = float2{(float)std::cos(a), (float)std::sin(a)};
+    }
+    up(pl->d_tw64, t64.data(), sizeof(double2) * g.nt);
+    up(pl->d_tw32, t32.data(), sizeof(float2) * g.nt);
+    std::vector<double2> lam(2 * g.F);
+    for (int n = 0; n < g.F; ++n) {
+      lam[n] = double2{pl->lam1[n].real(), pl->lam1[n].imag()};
+      lam[g.F + n] = double2{pl->lam2[n].real(), pl->lam2[n].imag()};
+    }
+    up(pl->d_lam, lam.data(), sizeof(double2) * 2 * g.F);
+  }
+  if (pl->p.dim == 2) {
+    const int n = g.nx;
+    for (int v = 0; v < 2; ++v) {
+      SpaceOp& op = pl->op[v];
+      std::vector<double2> tk(n);
+      for (int k = 0; k < n; ++k) tk[k] = double2{op.Tm[(size_t)k * n + k].real(), op.Tm[(size_t)k * n + k].imag()};
+      op.tk = (const double2*)take(sizeof(double2) * n);
+      up((void*)op.tk, tk.data(), sizeof(double2) * n);
+      // GEMM matrices: out = in * G, stored Bt[col][k]
+      std::vector<double> gf, gi;
+      const size_t ce = compute_elem_bytes(pl->prec);
+      if (!pl->schur) {
+        gf.resize((size_t)n * n);
+        gi.resize((size_t)n * n);
+        for (int c = 0; c < n; ++c)
+          for (int k = 0; k < n; ++k) {
+            gf[(size_t)c * n + k] = op.Q[(size_t)k * n + c].real();          // G = conj(Q) = Q
+            gi[(size_t)c * n + k] = op.Q[(size_t)c * n + k].real();          // G = Q^T
+          }
+      } else {
+        const int n2 = 2 * n;
+        gf.resize((size_t)n2 * n2);
+        gi.resize((size_t)n2 * n2);
+        auto fill = [&](std::vector<double>& Bt, auto G) {
+          // real block matrix M = [[Gr, Gi], [-Gi, Gr]] (row index k, column j); Bt[j][k] = M[k][j]
+          for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) {
+              cd v = G(k, j);
+              Bt[(size_t)j * n2 + k] = v.real();
+              Bt[(size_t)(j + n) * n2 + k] = v.imag();
+              Bt[(size_t)j * n2 + (k + n)] = -v.imag();
+              Bt[(size_t)(j + n) * n2 + (k + n)] = v.real();
+            }
+        };
+        fill(gf, [&](int k, int j) { return std::conj(op.Q[(size_t)k * n + j]); });
+        fill(gi, [&](int k, int j) { return op.Q[(size_t)j * n + k]; });
+      }
+      op.g_fwd = take(gf.size() * ce);
+      op.g_inv = take(gi.size() * ce);
+      if (pl->prec == Prec::F64) { store_compute<double>((void*)op.g_fwd, gf, s, keep); store_compute<double>((void*)op.g_inv, gi, s, keep); }
+      else if (pl->prec == Prec::F32) { store_compute<float>((void*)op.g_fwd, gf, s, keep); store_compute<float>((void*)op.g_inv, gi, s, keep); }
+      else { store_compute<Bf16Bits>((void*)op.g_fwd, gf, s, keep); store_compute<Bf16Bits>((void*)op.g_inv, gi, s, keep); }
+      if (pl->schur) {
+        std::vector<double> tp(2 * (size_t)n * n);
+        for (size_t i = 0; i < (size_t)n * n; ++i) { tp[i] = op.Tm[i].real(); tp[(size_t)n * n + i] = op.Tm[i].imag(); }
+        op.tup = take(tp.size() * spec_elem_bytes(pl->prec));
+        if (pl->prec == Prec::F64) store_compute<double>((void*)op.tup, tp, s, keep);
+        else store_compute<float>((void*)op.tup, tp, s, keep);
+      } else {
+        op.tup = nullptr;
+      }
+    }
+  }
+  pl->spec_a = take((size_t)g.spec_elems * spec_elem_bytes(pl->prec));
+  pl->spec_b = take((size_t)g.spec_elems * spec_elem_bytes(pl->prec));
+  pl->solver_base = p;
+  pl->ws = (char*)workspace;
+  pl->ws_bytes = bytes;
+  pl->bound = true;
+  hipError_t e = hipStreamSynchronize(s);   // host staging buffers must outlive the copies
+  if (e != hipSuccess) { set_error(std::string("bind: ") + hipGetErrorString(e)); return PD_ERR_HIP; }
+  return PD_OK;
+}
+
+static Plan* ready(paradiag_plan plan) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl) { set_error("plan is NULL"); return nullptr; }
+  if (!pl->bound) { set_error("no workspace bound"); return nullptr; }
+  return pl;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return a && b && x < y + nb && y < x + na;
+}
+
+paradiag_status paradiag_build_rhs(paradiag_plan plan, const double* U0, const double* u1,
+                                   const double* f, double* b, void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!U0 || !b) { set_error("U0 and b are required"); return PD_ERR_INVALID; }
+  build_rhs(*pl, U0, pl->p.scheme == PD_LEAPFROG ? u1 : nullptr, f, b, (hipStream_t)stream);
+  return check_hip("build_rhs");
+}
+
+paradiag_status paradiag_rhs_transpose(paradiag_plan plan, const double* lam, double* gU0,
+                                       double* gu1, double* gf, void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!lam || !gU0) { set_error("lam and gU0 are required"); return PD_ERR_INVALID; }
+  rhs_transpose(*pl, lam, gU0, gu1, gf, (hipStream_t)stream);
+  return check_hip("rhs_transpose");
+}
+
+paradiag_status paradiag_matvec(paradiag_plan plan, const double* u, double* y, int32_t transpose,
+                                void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!u || !y) { set_error("NULL vector"); return PD_ERR_INVALID; }
+  size_t nb = sizeof(double) * (size_t)pl->g.NA;
+  if (overlap(u, nb, y, nb)) { set_error("u and y overlap"); return PD_ERR_INVALID; }
+  apply_A(*pl, transpose ? 1 : 0, u, false, nullptr, y, (hipStream_t)stream);
+  return check_hip("matvec");
+}
+
+paradiag_status paradiag_apply_precond(paradiag_plan plan, const double* r, double* z,
+                                       void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!r || !z) { set_error("NULL vector"); return PD_ERR_INVALID; }
+  size_t nb = sizeof(double) * (size_t)pl->g.NA;
+  if (r != z && overlap(r, nb, z, nb)) { set_error("r and z partially overlap"); return PD_ERR_INVALID; }
+  apply_prec(*pl, 0, r, nullptr, z, false, 0, (hipStream_t)stream);
+  return check_hip("apply_precond");
+}
+
+static paradiag_status solve_entry(paradiag_plan plan, int variant, const double* b, double* u,
+                                   const paradiag_solve_opts* opts, paradiag_solve_info* info,
+                                   void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!b || !u || !opts) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (opts->mode < 0 || opts->mode > 2) { set_error("unknown mode"); return PD_ERR_INVALID; }
+  if (opts->mode == PD_MODE_FGMRES && (opts->restart < 1 || opts->restart > 32)) {
+    set_error("restart must be in [1, 32]"); return PD_ERR_INVALID;
+  }
+  if (opts->max_iter < 1 || !(opts->rtol > 0)) { set_error("max_iter >= 1 and rtol > 0 required"); return PD_ERR_INVALID; }
+  size_t nb = sizeof(double) * (size_t)pl->g.NA;
+  if (overlap(b, nb, u, nb)) { set_error("b and u overlap"); return PD_ERR_INVALID; }
+  try {
+    return solve_impl(*pl, variant, b, u, opts, info, (hipStream_t)stream);
+  } catch (...) {
+    set_error("solve failed (host allocation)");
+    return PD_ERR_INVALID;
+  }
+}
+
+paradiag_status paradiag_solve(paradiag_plan plan, const double* b, double* u,
+                               const paradiag_solve_opts* opts, paradiag_solve_info* info,
+                               void* stream) {
+  return solve_entry(plan, 0, b, u, opts, info, stream);
+}
+
+paradiag_status paradiag_adjoint_solve(paradiag_plan plan, const double* g, double* lam,
+                                       const paradiag_solve_opts* opts,
+                                       paradiag_solve_info* info, void* stream) {
+  return solve_entry(plan, 1, g, lam, opts, info, stream);
+}
+
+paradiag_status paradiag_get_xbasis(paradiag_plan plan, int32_t adjoint, double* q, double* t) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl || !q || !t) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (pl->p.dim != 2) { set_error("the x basis exists only in two dimensions"); return PD_ERR_INVALID; }
+  const SpaceOp& op = pl->op[adjoint ? 1 : 0];
+  for (size_t i = 0; i < op.Q.size(); ++i) {
+    q[2 * i] = op.Q[i].real(); q[2 * i + 1] = op.Q[i].imag();
+    t[2 * i] = op.Tm[i].real(); t[2 * i + 1] = op.Tm[i].imag();
+  }
+  return PD_OK;
+}
+
+paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* lam2) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl || !lam1 || !lam2) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  for (int n = 0; n < pl->g.F; ++n) {
+    lam1[2 * n] = pl->lam1[n].real(); lam1[2 * n + 1] = pl->lam1[n].imag();
+    lam2[2 * n] = pl->lam2[n].real(); lam2[2 * n + 1] = pl->lam2[n].imag();
+  }
+  return PD_OK;
+}
+
+paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl) { set_error("plan is NULL"); return PD_ERR_INVALID; }
+  pl->timer.enabled = enable != 0;
+  return PD_OK;
+}
+
+paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,
+                                         int32_t reset) {
+  Plan* pl = reinterpret_cast<Plan*>(plan);
+  if (!pl) { set_error("plan is NULL"); return PD_ERR_INVALID; }
+  drain_timer(*pl);
+  for (int i = 0; i < PD_NUM_STAGES; ++i) {
+    if (ms) ms[i] = pl->timer.ms[i];
+    if (counts) counts[i] = pl->timer.count[i];
+    if (reset) { pl->timer.ms[i] = 0; pl->timer.count[i] = 0; }
+  }
+  return check_hip("stage times");
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal declarations of the ParaDiag-II library (not part of the ABI).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/paradiag.h"
+
+namespace pd {
+
+using cd = std::complex<double>;
+
+bool complex_schur(int n, std::vector<cd>& h, std::vector<cd>& q);
+
+// Numeric formats of the preconditioner.
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Geometry of the spectral buffer [batch][F][sy][2][sx]: F = nt/2 + 1
+// frequencies, each slice a sy x sx complex field stored row-planar (a row
+// of sx real parts followed by sx imaginary parts).  In 2D (sy, sx) =
+// (ny, nx); in 1D the single line of nx points is stored as (sy, sx) =
+// (nx, 1) so that Step-(b) always solves along the "y" index.
+struct Geom {
+  int B, nt, F;
+  int nx, ny;     // physical grid
+  int sx, sy;     // spectral slice shape
+  int64_t S;      // nx * ny
+  int64_t N1;     // nt * S: one right-hand side
+  int64_t NA;     // B * N1
+  int64_t spec_elems;  // B * F * sy * 2 * sx
+};
+
+// Tables of one spatial operator (K, or K^T for the adjoint).
+struct SpaceOp {
+  // 5-point stencil of K at a point: K u = sxl u[x-1] + sxu u[x+1] + syl u[y-1] + syu u[y+1] + sd u
+  double sxl, sxu, syl, syu, sd;
+  // line operator solved in Step-(b) along the spectral y index: tridiag(lo, di, up)
+  double lo, di, up;
+  // x-direction basis (2D): per-mode shift t_k (complex), GEMM matrices stored
+  // transposed ([N][K], K contiguous) in the compute format, upper part of T.
+  const double2* tk = nullptr;
+  const void* g_fwd = nullptr;  // S -> S * conj(Q)
+  const void* g_inv = nullptr;  // W -> W * Q^T
+  const void* tup = nullptr;    // Schur T (planar re/im, [2][nx][nx], compute format); null if diagonal
+  // host copies
+  std::vector<cd> Q, Tm;        // nx*nx complex (row-major): K_x = Q T Q^H
+};
+
+struct Workspace;
+
+struct StageTimer {
+  bool enabled = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[PD_NUM_STAGES] = {0};
+  int64_t count[PD_NUM_STAGES] = {0};
+};
+
+struct Plan {
+  paradiag_problem p;
+  Geom g;
+  Prec prec;
+  bool schur = false;     // non-normal x factor: Schur back-sweep in Step-(b)
+  int L = 2;              // bands of the time stencil
+  double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+  double theta = 1.0;
+  std::vector<cd> lam1, lam2;      // nt/2+1 time symbols
+  std::vector<double> gam, invgam; // alpha^{n/nt} and alpha^{-n/nt}/nt
+  SpaceOp op[2];                   // [0] = K, [1] = K^T
+
+  // device (carved from the bound workspace)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  size_t ws_solver_bytes = 0;      // part of the workspace usable by the solvers
+  // tables
+  double* d_gam = nullptr;
+  double* d_invgam = nullptr;
+  double2* d_tw64 = nullptr;
+  float2* d_tw32 = nullptr;
+  double2* d_lam = nullptr;        // [2][F]
+  // spectral buffers
+  void* spec_a = nullptr;
+  void* spec_b = nullptr;
+  // solver scratch (start of the solver region)
+  char* solver_base = nullptr;
+  StageTimer timer;
+};
+
+size_t spec_elem_bytes(Prec p);          // 8 (double) or 4 (float)
+size_t tables_bytes(const Plan& pl);     // device tables + spectral buffers
+size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o);
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------- kernels
+struct Launch { hipStream_t stream; };
+
+// Step-(a): spec = rfft_t(Gamma * scale_b * x) ; x float64 [B][nt][S].
+// reverse != 0 reads x with time reversed (adjoint).
+void fft_time_forward(const Plan& pl, const double* x, const double* bscale, void* spec,
+                      int reverse, hipStream_t s);
+// Step-(c): z = Gamma^{-1} irfft_t(spec) (float64 or float32 output), optional accumulate.
+void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, int accumulate,
+                      int reverse, hipStream_t s);
+// Step-(b) pieces
+void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
+           hipStream_t s);
+void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
+void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
+// all-at-once operator
+void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
+            double* y, int transpose, hipStream_t s);
+void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,
+               hipStream_t s);
+void rhs_transpose(const Plan& pl, const double* lam, double* gU0, double* gu1, double* gf,
+                   hipStream_t s);
+// Krylov helpers (float64).  Vectors of one batch entry are N1 long and the
+// batch stride of every vector is N1.
+int dot_chunks(const Plan& pl);
+void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* w,
+               double* partial, hipStream_t s);
+// h[b][i] = t s, coef[b][i] = t s^2 with t the reduced dot and s = sigma[b][i]
+// for i < nscaled (else 1): dots against unnormalised Krylov vectors.
+void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
+                     int nscaled, double* h, double* coef, hipStream_t s);
+void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
+                double* w, double* partial, int want_dots, hipStream_t s);
+void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
+              const double* y, double* x, hipStream_t s);
+void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);
+void fill_zero(double* dst, int64_t n, hipStream_t s);
+
+}  // namespace pd

@@ -1,0 +1,375 @@
+// float64 kernels around the preconditioner: the all-at-once matvec (eq1.1),
+// the right-hand side (eq2.5, eq3.2) and its transpose, and the Krylov
+// vector operations of flexible GMRES.
+//
+// Matvec: y_n = sum_k c1_k u_{n-k} + K (sum_k c2_k u_{n-k}), u_{m<1} = 0,
+// with the 5-point stencil of K evaluated on the fly.  A workgroup owns 256
+// spatial points of one right-hand side and a chunk of consecutive time
+// steps; each thread marches through the chunk keeping the last L values of
+// u and K u of its point in registers, so u is read once (plus the L-1 steps
+// before the chunk) and y written once.  The transposed operator marches
+// backwards in time with the transposed stencil.
+//
+// Krylov reductions are deterministic: per-workgroup partial sums in a fixed
+// order, then a fixed-order reduction over workgroups.  No atomics.
+
+#include "internal.h"
+
+namespace pd {
+namespace {
+
+constexpr int NT = 256;
+
+struct Stencil {
+  double xl, xu, yl, yu, d;  // K u = xl u[x-1] + xu u[x+1] + yl u[y-1] + yu u[y+1] + d u
+};
+
+template <typename Tin>
+__device__ __forceinline__ double ld(const Tin* p) { return (double)*p; }
+
+template <typename Tin>
+__device__ __forceinline__ void point_and_k(const Tin* un, int x, int y, int nx, int ny,
+                                            const Stencil& st, double& u, double& ku) {
+  const Tin* c = un + (int64_t)y * nx + x;
+  u = ld(c);
+  double k = st.d * u;
+  if (x > 0) k += st.xl * ld(c - 1);
+  if (x < nx - 1) k += st.xu * ld(c + 1);
+  if (y > 0) k += st.yl * ld(c - nx);
+  if (y < ny - 1) k += st.yu * ld(c + nx);
+  ku = k;
+}
+
+// dir = +1: y = A u ;  dir = -1: y = A^T u (stencil already transposed by the caller).
+template <typename Tin>
+__global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const double* __restrict__ b,
+                                               double* __restrict__ yv, int Nt, int nx, int ny, int L,
+                                               double c10, double c11, double c12, double c20,
+                                               double c21, double c22, Stencil st, int chunk, int dir) {
+  const int S = nx * ny;
+  const int s = blockIdx.x * NT + threadIdx.x;
+  if (s >= S) return;
+  const int x = s % nx, y = s / nx;
+  const int64_t boff = (int64_t)blockIdx.z * Nt * S;
+  const Tin* ub = u + boff;
+  double* yb = yv + boff;
+  const double* bb = b ? b + boff : nullptr;
+  const int nbeg = blockIdx.y * chunk;
+  const int nend = min(Nt, nbeg + chunk);
+  double u1 = 0, k1 = 0, u2 = 0, k2 = 0;  // history: step -1 and -2 along the march
+  // prologue: the L-1 steps preceding the chunk in marching order
+  for (int h = L - 1; h >= 1; --h) {
+    int m = (dir > 0) ? (nbeg - h) : (nend - 1 + h);
+    double uu = 0, kk = 0;
+    if (m >= 0 && m < Nt) point_and_k(ub + (int64_t)m * S, x, y, nx, ny, st, uu, kk);
+    u2 = u1; k2 = k1; u1 = uu; k1 = kk;
+  }
+  for (int i = 0; i < nend - nbeg; ++i) {
+    int n = (dir > 0) ? (nbeg + i) : (nend - 1 - i);
+    double u0, k0;
+    point_and_k(ub + (int64_t)n * S, x, y, nx, ny, st, u0, k0);
+    double r = c10 * u0 + c20 * k0 + c11 * u1 + c21 * k1;
+    if (L > 2) r += c12 * u2 + c22 * k2;
+    int64_t off = (int64_t)n * S + s;
+    yb[off] = bb ? (bb[off] - r) : r;
+    u2 = u1; k2 = k1; u1 = u0; k1 = k0;
+  }
+}
+
+// b from U0, u1, f (see paradiag_build_rhs); one thread per (n, point).
+__global__ __launch_bounds__(NT) void k_rhs(const double* __restrict__ U0, const double* __restrict__ V1,
+                                            const double* __restrict__ f, double* __restrict__ b,
+                                            int Nt, int nx, int ny, int scheme, double dt,
+                                            double theta, Stencil st) {
+  const int S = nx * ny;
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int bi = blockIdx.y;
+  if (e >= (int64_t)Nt * S) return;
+  const int n = (int)(e / S), s = (int)(e - (int64_t)n * S);
+  const int x = s % nx, y = s / nx;
+  const double* u0b = U0 + (int64_t)bi * S;
+  const double* fb = f ? f + (int64_t)bi * (Nt + 1) * S : nullptr;
+  double r = 0.0;
+  double uu, ku;
+  if (scheme != PD_LEAPFROG) {
+    if (n == 0) {
+      point_and_k(u0b, x, y, nx, ny, st, uu, ku);
+      r = uu / dt - (1.0 - theta) * ku;
+    }
+    if (fb) r += theta * fb[(int64_t)(n + 1) * S + s] + (1.0 - theta) * fb[(int64_t)n * S + s];
+  } else {
+    if (n == 0) {
+      point_and_k(u0b, x, y, nx, ny, st, uu, ku);
+      r = uu / (dt * dt);
+      if (V1) {
+        double vv, kv;
+        point_and_k(V1 + (int64_t)bi * S, x, y, nx, ny, st, vv, kv);
+        r += vv / dt + 0.5 * dt * kv;
+      }
+      if (fb) r += 0.5 * fb[s];
+    } else if (n == 1) {
+      point_and_k(u0b, x, y, nx, ny, st, uu, ku);
+      r = -uu / (dt * dt) - 0.5 * ku;
+      if (fb) r += fb[(int64_t)S + s];
+    } else {
+      if (fb) r = fb[(int64_t)n * S + s];
+    }
+  }
+  b[(int64_t)bi * Nt * S + e] = r;
+}
+
+// Transpose of the right-hand side map; st is the transposed stencil.
+// One thread per (level n in 0..Nt, point): writes gf[n] and, at n == 0, gU0 / gu1.
+__global__ __launch_bounds__(NT) void k_rhs_t(const double* __restrict__ lam, double* __restrict__ gU0,
+                                              double* __restrict__ gu1, double* __restrict__ gf,
+                                              int Nt, int nx, int ny, int scheme, double dt,
+                                              double theta, Stencil st) {
+  const int S = nx * ny;
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int bi = blockIdx.y;
+  if (e >= (int64_t)(Nt + 1) * S) return;
+  const int n = (int)(e / S), s = (int)(e - (int64_t)n * S);
+  const int x = s % nx, y = s / nx;
+  const double* lb = lam + (int64_t)bi * Nt * S;   // lam_1 .. lam_Nt at rows 0..Nt-1
+  auto L = [&](int m) { return (m >= 1 && m <= Nt) ? lb[(int64_t)(m - 1) * S + s] : 0.0; };
+  if (scheme != PD_LEAPFROG) {
+    if (gf) gf[(int64_t)bi * (Nt + 1) * S + e] = theta * L(n) + (1.0 - theta) * L(n + 1);
+    if (n == 0) {
+      double l1, kl1;
+      point_and_k(lb, x, y, nx, ny, st, l1, kl1);
+      gU0[(int64_t)bi * S + s] = l1 / dt - (1.0 - theta) * kl1;
+      if (gu1) gu1[(int64_t)bi * S + s] = 0.0;
+    }
+  } else {
+    if (gf) {
+      double v = (n == 0) ? 0.5 * L(1) : (n < Nt ? L(n + 1) : 0.0);
+      gf[(int64_t)bi * (Nt + 1) * S + e] = v;
+    }
+    if (n == 0) {
+      double l1, kl1, l2 = 0, kl2 = 0;
+      point_and_k(lb, x, y, nx, ny, st, l1, kl1);
+      if (Nt > 1) point_and_k(lb + S, x, y, nx, ny, st, l2, kl2);
+      gU0[(int64_t)bi * S + s] = l1 / (dt * dt) - l2 / (dt * dt) - 0.5 * kl2;
+      if (gu1) gu1[(int64_t)bi * S + s] = l1 / dt + 0.5 * dt * kl1;
+    }
+  }
+}
+
+// ----------------------------------------------------------- Krylov helpers
+constexpr int MAXV = 33;  // vectors per multi-dot (restart <= 32)
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // wave reduction then across the 4 waves (fixed order)
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
+  return t;
+}
+
+// partial[b][chunk][i] = sum over the chunk of V_i[b] . w[b]  (i < nv)
+__global__ __launch_bounds__(NT) void k_mdot(const double* __restrict__ V, int64_t vstride, int nv,
+                                             const double* __restrict__ w, double* __restrict__ partial,
+                                             int64_t N1, int chunks) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int64_t per = (N1 + chunks - 1) / chunks;
+  const int64_t beg = c * per, end = min(N1, beg + per);
+  const double* wb = w + (int64_t)b * N1;
+  double acc[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) acc[i] = 0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+    double wv = wb[e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < nv) acc[i] += V[i * vstride + (int64_t)b * N1 + e] * wv;
+  }
+  double* out = partial + ((int64_t)b * chunks + c) * MAXV;
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    if (i < nv) {  // nv is uniform: the barrier inside is reached by all threads
+      double t = block_sum(acc[i], red);
+      if (threadIdx.x == 0) out[i] = t;
+    }
+  }
+}
+
+// t = sum_c partial[b][c][i]; with the Krylov scale s = sigma[b][i] (1 for
+// i >= nscaled or sigma == null): h[b][i] = t s and coef[b][i] = t s^2.
+__global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partial, int nv, int chunks,
+                                               const double* __restrict__ sigma, int nscaled,
+                                               double* __restrict__ h, double* __restrict__ coef,
+                                               int ldh) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, i = blockIdx.x;
+  double v = 0;
+  for (int c = threadIdx.x; c < chunks; c += NT) v += partial[((int64_t)b * chunks + c) * MAXV + i];
+  double t = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    double sg = (sigma && i < nscaled) ? sigma[b * ldh + i] : 1.0;
+    h[b * ldh + i] = t * sg;
+    if (coef) coef[b * ldh + i] = t * sg * sg;
+  }
+}
+
+// w[b] -= sum_i coef[b][i] V_i[b]; optionally partial dots of the new w with
+// V_i (slots 0..nv-1) and with itself (slot nv).
+__global__ __launch_bounds__(NT) void k_update(const double* __restrict__ V, int64_t vstride, int nv,
+                                               const double* __restrict__ coef, int ldc,
+                                               double* __restrict__ w, double* __restrict__ partial,
+                                               int64_t N1, int chunks, int want_dots) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int64_t per = (N1 + chunks - 1) / chunks;
+  const int64_t beg = c * per, end = min(N1, beg + per);
+  double* wb = w + (int64_t)b * N1;
+  double cf[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) cf[i] = (i < nv) ? coef[b * ldc + i] : 0.0;
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i) acc[i] = 0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+    double vv[MAXV];
+    double wv = wb[e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < nv) {
+        vv[i] = V[i * vstride + (int64_t)b * N1 + e];
+        wv -= cf[i] * vv[i];
+      }
+    wb[e] = wv;
+    if (want_dots) {
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i)
+        if (i < nv) acc[i] += vv[i] * wv;
+      acc[MAXV] += wv * wv;
+    }
+  }
+  if (!want_dots) return;
+  double* out = partial + ((int64_t)b * chunks + c) * MAXV;
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    if (i < nv) {
+      double t = block_sum(acc[i], red);
+      if (threadIdx.x == 0) out[i] = t;
+    }
+  }
+  double t = block_sum(acc[MAXV], red);
+  if (threadIdx.x == 0) out[nv] = t;
+}
+
+// x[b] += sum_i y[b][i] Z_i[b]
+template <typename Tz>
+__global__ __launch_bounds__(NT) void k_xupd(const Tz* __restrict__ Z, int64_t zstride, int nz,
+                                             const double* __restrict__ yc, int ldy,
+                                             double* __restrict__ x, int64_t N1) {
+  const int b = blockIdx.y;
+  double cf[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) cf[i] = (i < nz) ? yc[b * ldy + i] : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < N1; e += (int64_t)gridDim.x * NT) {
+    double v = x[(int64_t)b * N1 + e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < nz) v += cf[i] * (double)Z[i * zstride + (int64_t)b * N1 + e];
+    x[(int64_t)b * N1 + e] = v;
+  }
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) b[e] = a[e];
+}
+__global__ void k_zero(double* __restrict__ b, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) b[e] = 0.0;
+}
+
+Stencil stencil_of(const SpaceOp& op) { return Stencil{op.sxl, op.sxu, op.syl, op.syu, op.sd}; }
+
+int grid_for(int64_t n) {
+  int64_t g = (n + NT - 1) / NT;
+  if (g > 65536) g = 65536;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+}  // namespace
+
+void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
+            double* y, int transpose, hipStream_t s) {
+  const Geom& g = pl.g;
+  const int chunk = 16;
+  dim3 grid((g.S + NT - 1) / NT, (g.nt + chunk - 1) / chunk, g.B);
+  Stencil st = stencil_of(op);
+  int dir = transpose ? -1 : 1;
+  if (u_is_f32)
+    k_matvec<float><<<grid, NT, 0, s>>>((const float*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0],
+                                        pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,
+                                        chunk, dir);
+  else
+    k_matvec<double><<<grid, NT, 0, s>>>((const double*)u, b, y, g.nt, g.nx, g.ny, pl.L,
+                                         pl.c1[0], pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1],
+                                         pl.c2[2], st, chunk, dir);
+}
+
+void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,
+               hipStream_t s) {
+  const Geom& g = pl.g;
+  dim3 grid((unsigned)(((int64_t)g.nt * g.S + NT - 1) / NT), g.B);
+  k_rhs<<<grid, NT, 0, s>>>(U0, u1, f, b, g.nt, g.nx, g.ny, pl.p.scheme, pl.p.T / g.nt, pl.theta,
+                            stencil_of(pl.op[0]));
+}
+
+void rhs_transpose(const Plan& pl, const double* lam, double* gU0, double* gu1, double* gf,
+                   hipStream_t s) {
+  const Geom& g = pl.g;
+  dim3 grid((unsigned)(((int64_t)(g.nt + 1) * g.S + NT - 1) / NT), g.B);
+  k_rhs_t<<<grid, NT, 0, s>>>(lam, gU0, gu1, gf, g.nt, g.nx, g.ny, pl.p.scheme, pl.p.T / g.nt,
+                              pl.theta, stencil_of(pl.op[1]));
+}
+
+int dot_chunks(const Plan& pl) {
+  int64_t c = pl.g.N1 / (NT * 64);
+  if (c < 1) c = 1;
+  if (c > 2048) c = 2048;
+  return (int)c;
+}
+
+void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* w,
+               double* partial, hipStream_t s) {
+  int chunks = dot_chunks(pl);
+  k_mdot<<<dim3(chunks, pl.g.B), NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks);
+}
+
+void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
+                     int nscaled, double* h, double* coef, hipStream_t s) {
+  int chunks = dot_chunks(pl);
+  k_reduce<<<dim3(nv, pl.g.B), NT, 0, s>>>(partial, nv, chunks, sigma, nscaled, h, coef, MAXV);
+}
+
+void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
+                double* w, double* partial, int want_dots, hipStream_t s) {
+  int chunks = dot_chunks(pl);
+  k_update<<<dim3(chunks, pl.g.B), NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1,
+                                               chunks, want_dots);
+}
+
+void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
+              const double* y, double* x, hipStream_t s) {
+  dim3 grid(grid_for(pl.g.N1), pl.g.B);
+  if (z_is_f32)
+    k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1);
+  else
+    k_xupd<double><<<grid, NT, 0, s>>>((const double*)Z, zstride, nz, y, MAXV, x, pl.g.N1);
+}
+
+void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s) {
+  k_copy<<<grid_for(n), NT, 0, s>>>(src, dst, n);
+}
+
+void fill_zero(double* dst, int64_t n, hipStream_t s) { k_zero<<<grid_for(n), NT, 0, s>>>(dst, n); }
+
+}  // namespace pd

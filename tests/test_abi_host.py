@@ -1,0 +1,155 @@
+"""CPU checks of the C ABI: exports, argument validation and the host-side setup.
+
+No kernel is launched here; setup, workspace sizing and the table getters are
+host-only entry points.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import Problem, operators as ops
+from tests.conftest import ROOT
+
+pd_lib = pytest.importorskip("paper_2005_09158_amd._lib")
+
+
+def _lib():
+    if not os.path.exists(pd_lib.LIB_PATH):
+        pytest.skip("libparadiag.so not built")
+    return pd_lib.load()
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "paradiag.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(paradiag_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = _lib()
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pd_lib.SIGNATURES), set(names) ^ set(pd_lib.SIGNATURES)
+
+
+def _setup(**kw):
+    lib = _lib()
+    base = dict(dim=2, nx=16, ny=12, nt=32, batch=1, scheme=1, prec=0, reserved=0, T=1.0,
+                nu=5e-2, ax=1.0, ay=0.5, alpha=1e-2)
+    base.update(kw)
+    prob = pd_lib.Problem(**base)
+    h = ctypes.c_void_p()
+    st = lib.paradiag_setup(ctypes.byref(prob), ctypes.byref(h))
+    return lib, st, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(alpha=0.0), pd_lib.PD_ERR_INVALID),
+    (dict(alpha=1.5), pd_lib.PD_ERR_INVALID),
+    (dict(nt=24), pd_lib.PD_ERR_UNSUPPORTED),
+    (dict(nt=2), pd_lib.PD_ERR_UNSUPPORTED),
+    (dict(dim=3), pd_lib.PD_ERR_INVALID),
+    (dict(batch=0), pd_lib.PD_ERR_INVALID),
+    (dict(batch=65), pd_lib.PD_ERR_INVALID),
+    (dict(nu=-1.0), pd_lib.PD_ERR_INVALID),
+    (dict(scheme=7), pd_lib.PD_ERR_INVALID),
+    (dict(dim=1, ny=3), pd_lib.PD_ERR_INVALID),
+    (dict(reserved=1), pd_lib.PD_ERR_INVALID),
+    (dict(nu=1e-4), pd_lib.PD_ERR_UNSUPPORTED),    # cell Peclet number >= 1
+])
+def test_setup_rejects(kw, code):
+    lib, st, h = _setup(**kw)
+    assert st == code
+    assert h.value is None
+    assert len(lib.paradiag_last_error()) > 0
+
+
+def test_calls_without_workspace_fail_cleanly():
+    lib, st, h = _setup()
+    assert st == pd_lib.PD_OK
+    dummy = ctypes.c_void_p(16)
+    assert lib.paradiag_matvec(h, dummy, dummy, 0, None) == pd_lib.PD_ERR_WORKSPACE
+    assert lib.paradiag_apply_precond(h, dummy, dummy, None) == pd_lib.PD_ERR_WORKSPACE
+    assert lib.paradiag_matvec(None, dummy, dummy, 0, None) == pd_lib.PD_ERR_INVALID
+    lib.paradiag_destroy(h)
+
+
+def test_workspace_size_grows_with_restart():
+    lib, st, h = _setup()
+    sizes = []
+    for m in (1, 4, 16):
+        o = pd_lib.SolveOpts(mode=0, restart=m, max_iter=10, use_x0=0, rtol=1e-8)
+        n = ctypes.c_size_t()
+        assert lib.paradiag_workspace_size(h, ctypes.byref(o), ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    # one FP64 Krylov vector per extra restart step at least
+    assert sizes[2] - sizes[1] >= 12 * 8 * 16 * 12 * 32
+    lib.paradiag_destroy(h)
+
+
+@pytest.mark.parametrize("scheme,s", [(0, "be"), (1, "tr"), (2, "lf")])
+def test_time_symbols_match_oracle(scheme, s):
+    lib, st, h = _setup(scheme=scheme, nt=64, alpha=3e-3, ax=0.0 if s == "lf" else 1.0,
+                        ay=0.0 if s == "lf" else 0.5)
+    assert st == 0
+    F = 33
+    l1 = (ctypes.c_double * (2 * F))()
+    l2 = (ctypes.c_double * (2 * F))()
+    assert lib.paradiag_get_symbols(h, l1, l2) == 0
+    got1 = np.array(l1[:]).view(np.complex128)
+    got2 = np.array(l2[:]).view(np.complex128)
+    p = Problem(dim=2, nx=16, ny=12, nt=64, scheme=s, T=1.0, nu=5e-2, alpha=3e-3)
+    r1, r2 = ops.time_symbols(p)
+    np.testing.assert_allclose(got1, r1[:F], rtol=1e-12, atol=1e-12 * np.abs(r1).max())
+    np.testing.assert_allclose(got2, r2[:F], rtol=1e-12, atol=1e-14)
+    lib.paradiag_destroy(h)
+
+
+def _xbasis(lib, h, n, adjoint):
+    q = (ctypes.c_double * (2 * n * n))()
+    t = (ctypes.c_double * (2 * n * n))()
+    assert lib.paradiag_get_xbasis(h, adjoint, q, t) == 0
+    Q = np.array(q[:]).view(np.complex128).reshape(n, n)
+    T = np.array(t[:]).view(np.complex128).reshape(n, n)
+    return Q, T
+
+
+@pytest.mark.parametrize("n,nu,a", [(16, 5e-2, 1.0), (64, 1e-2, 1.0), (128, 5e-3, 1.0),
+                                    (256, 5e-3, 1.0), (512, 5e-3, 1.0)])
+def test_schur_basis_backward_stable(n, nu, a):
+    # K_x = Q T Q^H with Q unitary and T upper triangular (backward error ~ eps)
+    lib, st, h = _setup(nx=n, ny=8, nu=nu, ax=a, ay=0.01)
+    assert st == 0, lib.paradiag_last_error()
+    Kx = ops.k1d(n, nu, a).toarray()
+    for adj, K in ((0, Kx), (1, Kx.T)):
+        Q, T = _xbasis(lib, h, n, adj)
+        nrm = np.linalg.norm(K)
+        assert np.linalg.norm(Q @ T @ Q.conj().T - K) / nrm < 1e-13
+        assert np.linalg.norm(Q.conj().T @ Q - np.eye(n)) < 1e-12
+        assert np.abs(np.tril(T, -1)).max() == 0.0
+    lib.paradiag_destroy(h)
+
+
+def test_sine_basis_for_symmetric_factor():
+    lib, st, h = _setup(nx=20, ny=8, ax=0.0, ay=0.0, scheme=2)
+    assert st == 0
+    Q, T = _xbasis(lib, h, 20, 0)
+    K = ops.k1d(20, 5e-2, 0.0).toarray()
+    np.testing.assert_allclose(Q.real @ np.diag(np.diag(T).real) @ Q.real.T, K, atol=1e-11 * np.abs(K).max())
+    assert np.abs(Q.imag).max() == 0 and np.abs(T - np.diag(np.diag(T))).max() == 0
+    lib.paradiag_destroy(h)
+
+
+def test_xbasis_rejected_in_1d():
+    lib, st, h = _setup(dim=1, nx=32, ny=1, ax=1.0)
+    assert st == 0
+    q = (ctypes.c_double * 4)()
+    assert lib.paradiag_get_xbasis(h, 0, q, q) == pd_lib.PD_ERR_INVALID
+    lib.paradiag_destroy(h)
