@@ -1,0 +1,231 @@
+"""Benchmark: space-time unknowns per second to a 1e-8 relative residual on one MI355X.
+
+A step is one complete ParaDiag-II solve of the all-at-once system of the
+workload (right-hand side resident in HBM): flexible GMRES with the
+alpha-circulant preconditioner -- time FFTs, x-transforms, line solves or the
+Schur back-sweep, matvec, Gram-Schmidt -- until ||b - A u|| <= 1e-8 ||b||.
+The mixed-precision preconditioner (float32 FFT and line solves, bf16 MFMA
+x-transform) is timed next to the plain float64 one on the same problem;
+`value` is the mixed-precision rate.
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes or flops per launch over the average launch time, both measured by the
+library with HIP events on the solve's stream during the timed steps) and a
+CPU baseline: the float64 oracle's sequential time stepper on the same
+problem, timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "mfma_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 2500.0, "fp32_bf16x1": 2500.0},
+    "vector_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 157.3, "fp32_bf16x1": 157.3},
+}
+
+# bound of each stage of the library's accounting
+STAGE_BOUND = {"fft_fwd": "hbm", "fft_inv": "hbm", "line_solve": "hbm", "matvec": "hbm",
+               "dot": "hbm", "update": "hbm", "other": "hbm", "xform_fwd": "mfma",
+               "xform_inv": "mfma"}
+
+STAGE_KERNEL = {"fft_fwd": "k_fft_fwd", "fft_inv": "k_fft_inv", "line_solve": "k_line_solve",
+                "matvec": "k_matvec", "dot": "k_mdot", "update": "k_update", "other": "k_reduce",
+                "xform_fwd": "k_gemm", "xform_inv": "k_gemm"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--mixed", default="fp32_bf16gemm", choices=["fp32", "fp32_bf16gemm", "fp32_bf16x1"])
+    ap.add_argument("--restart", type=int, default=8)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    return ap.parse_args()
+
+
+def make_inputs(cfg, torch, pd):
+    from workloads import initial_state, initial_velocity, source_term_torch
+    U0 = torch.from_numpy(initial_state(cfg)).cuda()
+    U0 = U0.reshape(1, cfg.ny, cfg.nx).expand(cfg.batch, cfg.ny, cfg.nx).contiguous()
+    u1 = None
+    if cfg.scheme == "lf":
+        u1 = torch.from_numpy(initial_velocity(cfg)).cuda().reshape(1, cfg.ny, cfg.nx)
+        u1 = u1.expand(cfg.batch, cfg.ny, cfg.nx).contiguous()
+    f = None
+    if cfg.with_source:
+        f = torch.empty(pd.source_shape, dtype=torch.float64, device="cuda")
+        for s in range(cfg.batch):
+            f[s] = source_term_torch(cfg, cfg.seed + 1 + s, "cuda")
+    return U0, u1, f
+
+
+def run_precision(cfg, prec, args, torch):
+    from paper_2005_09158_amd import ParaDiag
+    pd = ParaDiag(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, scheme=cfg.scheme, T=cfg.T,
+                  nu=cfg.nu, ax=cfg.ax, ay=cfg.ay, alpha=cfg.alpha, batch=cfg.batch, prec=prec,
+                  restart=args.restart)
+    U0, u1, f = make_inputs(cfg, torch, pd)
+    b = pd.build_rhs(U0, u1, f)
+    del f
+    u = torch.empty_like(b)
+    for _ in range(args.warmup):
+        pd.solve(b, u, rtol=cfg.rtol, max_iter=200)
+    pd.set_timing(True)
+    pd.stage_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        _, res = pd.solve(b, u, rtol=cfg.rtol, max_iter=200)
+        results.append(res)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = pd.stage_times(reset=True)
+    pd.set_timing(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    out = dict(prec=prec, ms_per_step=ms, iters=[r.iters for r in results],
+               rel_resid=max(r.rel_resid for r in results),
+               converged=all(r.converged for r in results), stages=stages)
+    u_keep = u
+    del b
+    return out, pd, u_keep
+
+
+def roofline(run, cfg, traffic_file):
+    stages = run["stages"]
+    name = max(stages, key=lambda k: stages[k][0])
+    ms, cnt, by, fl = stages[name]
+    bound = STAGE_BOUND[name]
+    if name == "line_solve" and cfg.dim == 2 and cfg.ax != 0.0:
+        bound = "alu"   # Schur back-sweep: coupling products on the vector ALUs
+    avg_s = ms / 1e3 / max(cnt, 1)
+    if bound == "hbm":
+        achieved = by / max(cnt, 1) / avg_s / 1e9
+        peak, unit = PEAK["hbm_GBs"], "GB/s"
+    elif bound == "mfma":
+        achieved = fl / max(cnt, 1) / avg_s / 1e12
+        peak, unit = PEAK["mfma_TFs"][run["prec"]], "TFLOP/s"
+    else:
+        achieved = fl / max(cnt, 1) / avg_s / 1e12
+        peak, unit = PEAK["vector_TFs"][run["prec"]], "TFLOP/s"
+    traffic = None
+    if traffic_file and os.path.exists(traffic_file):
+        with open(traffic_file) as fh:
+            t = json.load(fh)
+        if t.get("kernel") == STAGE_KERNEL.get(name):
+            traffic = t.get("bytes_per_launch")
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": STAGE_KERNEL[name],
+            "stage": name, "launches": cnt, "avg_launch_ms": round(ms / max(cnt, 1), 5),
+            "algorithmic_bytes_per_launch": by / max(cnt, 1),
+            "algorithmic_flops_per_launch": fl / max(cnt, 1)}
+
+
+def cpu_baseline(cfg):
+    """The oracle's sequential float64 time stepper on one right-hand side (host, 1 thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import Problem, rhs, solve
+    from workloads import initial_state, initial_velocity, source_term
+    p = Problem.from_kwargs(**cfg.problem_kwargs())
+    nt_sample = p.nt
+    # bound the host work: at most ~2e7 space-time unknowns (cfg3/cfg5 solve a prefix of
+    # the time steps; the stepper's cost is linear in the number of steps)
+    while nt_sample * p.nspace > 4e7 and nt_sample > 16:
+        nt_sample //= 2
+    with threadpool_limits(1):
+        U0 = initial_state(cfg)
+        f = source_term(cfg, cfg.seed + 1) if cfg.with_source else None
+        u1 = initial_velocity(cfg) if cfg.scheme == "lf" else None
+        b = rhs.build_rhs(p, U0, u1, f)
+        t0 = time.perf_counter()
+        ps = Problem.from_kwargs(**{**cfg.problem_kwargs(), "nt": nt_sample,
+                                   "T": cfg.T * nt_sample / cfg.nt})
+        solve.sequential(ps, b[:nt_sample])
+        dt = time.perf_counter() - t0
+    return {"value": nt_sample * p.nspace / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential float64 time stepping (one sparse LU + {nt_sample} triangular "
+                      f"solves) of 1 right-hand side, {nt_sample} of {p.nt} steps, "
+                      f"{p.nspace} unknowns per step; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
+              f"single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from workloads import CONFIGS
+    cfg = CONFIGS[args.workload]
+    torch.cuda.set_device(0)
+    print(f"[bench] workload {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nt} batch {cfg.batch} "
+          f"scheme {cfg.scheme} alpha {cfg.alpha}", file=sys.stderr, flush=True)
+    mixed, pdm, _ = run_precision(cfg, args.mixed, args, torch)
+    print(f"[bench] {args.mixed}: {mixed['ms_per_step']:.3f} ms/solve iters {mixed['iters']} "
+          f"resid {mixed['rel_resid']:.2e}", file=sys.stderr, flush=True)
+    del pdm
+    torch.cuda.empty_cache()
+    fp64 = None
+    if not args.skip_fp64:
+        fp64, pd64, _ = run_precision(cfg, "fp64", args, torch)
+        del pd64
+        torch.cuda.empty_cache()
+        print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/solve iters {fp64['iters']} "
+              f"resid {fp64['rel_resid']:.2e}", file=sys.stderr, flush=True)
+    U = cfg.unknowns
+    value = U / (mixed["ms_per_step"] / 1e3)
+    line = {
+        "metric": "space-time unknowns/s to 1e-8 residual, mixed-prec vs FP64 ParaDiag-II, 1 GPU",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32_bf16gemm": "f64 krylov + f32 fft/line solves + split-bf16 mfma x-transform",
+                  "fp32_bf16x1": "f64 krylov + f32 fft/line solves + bf16 mfma x-transform",
+                  "fp32": "f64 krylov + f32 preconditioner"}[args.mixed],
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: 2D advection-diffusion {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, "
+                               f"{cfg.scheme.upper()}, alpha {cfg.alpha}, batch {cfg.batch}"
+                   if cfg.dim == 2 else f"{cfg.name}", "nx": cfg.nx, "ny": cfg.ny, "nt": cfg.nt,
+                   "batch": cfg.batch, "unknowns": U, "rtol": cfg.rtol, "restart": args.restart},
+        "mixed": {k: v for k, v in mixed.items() if k != "stages"},
+        "fp64": None if fp64 is None else {k: v for k, v in fp64.items() if k != "stages"},
+        "fp64_value": None if fp64 is None else U / (fp64["ms_per_step"] / 1e3),
+        "mixed_speedup_vs_fp64": None if fp64 is None else fp64["ms_per_step"] / mixed["ms_per_step"],
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in mixed["stages"].items()},
+        "stage_ms_per_step_fp64": None if fp64 is None else
+        {k: round(v[0] / args.steps, 4) for k, v in fp64["stages"].items()},
+        "roofline": roofline(mixed, cfg, args.traffic),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

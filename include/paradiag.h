@@ -71,7 +71,12 @@ typedef enum { PD_BE = 0, PD_TR = 1, PD_LEAPFROG = 2 } paradiag_scheme;
 typedef enum {
   PD_PREC_FP64 = 0,           /* FFT, x-transform and line solves in float64 */
   PD_PREC_FP32 = 1,           /* FFT, x-transform and line solves in float32 */
-  PD_PREC_FP32_BF16GEMM = 2   /* as FP32, x-transform on bf16 MFMA with fp32 accumulation */
+  PD_PREC_FP32_BF16GEMM = 2,  /* as FP32; x-transform on bf16 MFMA with fp32 accumulation,
+                                 operands split into bf16 hi + lo parts (three products:
+                                 float32-level accuracy at bf16 instruction rate) */
+  PD_PREC_FP32_BF16X1 = 3     /* as FP32; x-transform as one bf16 product (fastest, least
+                                 accurate: the preconditioner error grows with the
+                                 non-normality of K_x) */
 } paradiag_prec;
 
 typedef enum {
@@ -82,7 +87,8 @@ typedef enum {
 
 typedef struct {
   int32_t dim;        /* 1 or 2 */
-  int32_t nx, ny;     /* interior points per direction; ny = 1 when dim = 1; nx, ny in [1, 4096] */
+  int32_t nx, ny;     /* interior points per direction; ny = 1 when dim = 1; nx, ny in [1, 2048]
+                       (nx <= 1024 when ax != 0: host Schur cost) */
   int32_t nt;         /* time steps: a power of two in [4, 4096] */
   int32_t batch;      /* independent right-hand sides, 1..64 */
   int32_t scheme;     /* paradiag_scheme */
@@ -96,7 +102,7 @@ typedef struct {
 
 typedef struct {
   int32_t mode;       /* paradiag_mode */
-  int32_t restart;    /* FGMRES cycle length m, 1..64 (ignored otherwise) */
+  int32_t restart;    /* FGMRES cycle length m, 1..32 (ignored otherwise) */
   int32_t max_iter;   /* total preconditioner applications allowed, >= 1 */
   int32_t use_x0;     /* 1: u holds the initial guess on entry; 0: start from zero */
   double rtol;        /* target ||b - A u||_2 / ||b||_2 per right-hand side, > 0 */
@@ -123,7 +129,8 @@ typedef struct {
 paradiag_status paradiag_setup(const paradiag_problem* prob, paradiag_plan* out);
 
 /* Bytes of device workspace needed for calls with `opts` (opts may be NULL:
- * enough for matvec, apply_precond, build_rhs and PD_MODE_DIRECT).  Host only. */
+ * enough for matvec, apply_precond, build_rhs and rhs_transpose; solves need
+ * the size for their mode and restart).  Host only. */
 paradiag_status paradiag_workspace_size(paradiag_plan plan, const paradiag_solve_opts* opts,
                                         size_t* bytes);
 
@@ -180,17 +187,27 @@ paradiag_status paradiag_get_xbasis(paradiag_plan plan, int32_t adjoint, double*
 paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* lam2);
 
 /* Stage timing.  When enabled, every later call records HIP events around
- * each kernel launch on the call's stream; paradiag_get_stage_times returns,
- * per stage (see PD_STAGE_*), the summed milliseconds and launch counts since
- * the last reset (it synchronises on the recorded events). */
+ * each kernel launch on the call's own stream.  paradiag_get_stage_times
+ * returns, per stage (PD_STAGE_*), the summed milliseconds, the launch count
+ * and the algorithmic work of those launches since the last reset: bytes
+ * that must cross HBM at least once (inputs read once, outputs written once)
+ * and floating-point operations.  It synchronises on the recorded events.
+ * Any output pointer may be NULL. */
 enum {
-  PD_STAGE_FFT_FWD = 0, PD_STAGE_XFORM_FWD = 1, PD_STAGE_LINE_SOLVE = 2, PD_STAGE_XFORM_INV = 3,
-  PD_STAGE_FFT_INV = 4, PD_STAGE_MATVEC = 5, PD_STAGE_ORTHO = 6, PD_STAGE_OTHER = 7,
-  PD_NUM_STAGES = 8
+  PD_STAGE_FFT_FWD = 0,    /* Step-(a): scaled real-to-complex FFT along time */
+  PD_STAGE_XFORM_FWD = 1,  /* Step-(b): x-transform GEMM into the x basis */
+  PD_STAGE_LINE_SOLVE = 2, /* Step-(b): y line solves (or the Schur back-sweep) */
+  PD_STAGE_XFORM_INV = 3,  /* Step-(b): x-transform GEMM back */
+  PD_STAGE_FFT_INV = 4,    /* Step-(c): complex-to-real FFT along time, scaled */
+  PD_STAGE_MATVEC = 5,     /* all-at-once matvec (optionally fused b - A u) */
+  PD_STAGE_DOT = 6,        /* Krylov multi-dot products */
+  PD_STAGE_UPDATE = 7,     /* Krylov vector updates (fused with the next dots) */
+  PD_STAGE_OTHER = 8,      /* reductions of partial sums, solution update, copies */
+  PD_NUM_STAGES = 9
 };
 paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable);
 paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,
-                                         int32_t reset);
+                                         double* bytes, double* flops, int32_t reset);
 
 void paradiag_destroy(paradiag_plan plan);
 const char* paradiag_last_error(void);

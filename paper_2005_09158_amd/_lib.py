@@ -22,9 +22,10 @@ STATUS_NAMES = {0: "PD_OK", 1: "PD_NOT_CONVERGED", -1: "PD_ERR_INVALID", -2: "PD
                 -6: "PD_ERR_BREAKDOWN"}
 
 SCHEMES = {"be": 0, "tr": 1, "lf": 2}
-PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2}
+PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2, "fp32_bf16x1": 3}
 MODES = {"fgmres": 0, "stationary": 1, "direct": 2}
-STAGES = ["fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv", "matvec", "ortho", "other"]
+STAGES = ["fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv", "matvec", "dot", "update",
+          "other"]
 
 
 class Problem(ctypes.Structure):
@@ -65,7 +66,8 @@ SIGNATURES = {
     "paradiag_get_xbasis": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D]),
     "paradiag_get_symbols": (ctypes.c_int, [_P, _D, _D]),
     "paradiag_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
-    "paradiag_get_stage_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "paradiag_get_stage_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64), _D, _D,
+                                                ctypes.c_int32]),
     "paradiag_destroy": (None, [_P]),
     "paradiag_last_error": (ctypes.c_char_p, []),
     "paradiag_version": (ctypes.c_char_p, []),

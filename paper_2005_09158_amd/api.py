@@ -169,11 +169,15 @@ class ParaDiag:
         _lib.check(self.lib.paradiag_set_timing(self.plan, int(enable)), "paradiag_set_timing")
 
     def stage_times(self, reset: bool = True) -> dict:
-        ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_int64 * 8)()
-        _lib.check(self.lib.paradiag_get_stage_times(self.plan, ms, cnt, int(reset)),
+        """{stage: (ms, launches, algorithmic bytes, flops)} since the last reset."""
+        n = len(_lib.STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        by = (ctypes.c_double * n)()
+        fl = (ctypes.c_double * n)()
+        _lib.check(self.lib.paradiag_get_stage_times(self.plan, ms, cnt, by, fl, int(reset)),
                    "paradiag_get_stage_times")
-        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.STAGES)}
+        return {name: (ms[i], cnt[i], by[i], fl[i]) for i, name in enumerate(_lib.STAGES)}
 
     def __del__(self):
         try:

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libparadiag.so")
 
-SOURCES = ["api.cpp", "schur.cpp", "kernels_fft.hip", "kernels_tri.hip", "kernels_gemm.hip",
+SOURCES = ["api.cpp", "schur.cpp", "kernels_fft.hip", "kernels_tri.hip", "kernels_sweep.hip", "kernels_gemm.hip",
            "kernels_blas.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -23,6 +23,11 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 size_t compute_elem_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+// bytes of one x-transform matrix of `elems` entries in the compute format
+// (split bf16 keeps hi and lo parts plus a float32 copy for ragged sizes)
+size_t gemm_matrix_bytes(Prec p, size_t elems) {
+  return p == Prec::BF16 ? elems * (2 + 2 + 4) : elems * compute_elem_bytes(p);
+}
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -75,7 +80,7 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
     set_error("T and nu must be positive and finite"); return PD_ERR_INVALID;
   }
   if (p.scheme < 0 || p.scheme > 2) { set_error("unknown scheme"); return PD_ERR_INVALID; }
-  if (p.prec < 0 || p.prec > 2) { set_error("unknown precision"); return PD_ERR_INVALID; }
+  if (p.prec < 0 || p.prec > 3) { set_error("unknown precision"); return PD_ERR_INVALID; }
   if (p.reserved != 0) { set_error("reserved must be 0"); return PD_ERR_INVALID; }
   if (!is_pow2(p.nt) || p.nt < 4 || p.nt > 4096) {
     set_error("nt must be a power of two in [4, 4096]"); return PD_ERR_UNSUPPORTED;
@@ -174,6 +179,10 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
     if (!pl->schur) { Qa = Q; Ta = T; }
     pl->op[1].Q = Qa;
     pl->op[1].Tm = Ta;
+    if (pl->schur && (p.ny > 512 || schur_sweep_lds(*pl) > 160 * 1024)) {
+      set_error("non-symmetric x factor with ny > 512 unsupported (back-sweep tile exceeds LDS)");
+      return PD_ERR_UNSUPPORTED;
+    }
   }
   out = pl.release();
   return PD_OK;
@@ -191,7 +200,7 @@ size_t tables_bytes(const Plan& pl) {
     size_t gm = pl.schur ? (2 * n) * (2 * n) : n * n;
     for (int v = 0; v < 2; ++v) {
       b += align_up(sizeof(double2) * n);                             // tk
-      b += 2 * align_up(gm * compute_elem_bytes(pl.prec));            // g_fwd, g_inv
+      b += 2 * align_up(gemm_matrix_bytes(pl.prec, gm));              // g_fwd, g_inv
       if (pl.schur) b += align_up(2 * n * n * spec_elem_bytes(pl.prec));  // T (line precision)
     }
   }
@@ -219,8 +228,11 @@ struct Timed {
   int stage;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(Plan& p, int st, hipStream_t str) : pl(p), stage(st), s(str) {
+  Timed(Plan& p, int st, hipStream_t str, double bytes = 0, double flops = 0)
+      : pl(p), stage(st), s(str) {
     if (!pl.timer.enabled) return;
+    pl.timer.bytes[stage] += bytes;
+    pl.timer.flops[stage] += flops;
     a = take();
     b = take();
     hipEventRecord(a, s);
@@ -253,28 +265,53 @@ static void drain_timer(Plan& pl) {
 
 // ------------------------------------------------------------ operations
 
+// Algorithmic work of one launch of each kernel (bytes that must cross HBM
+// once, floating-point operations), used by the stage accounting.
+static double spec_bytes(const Plan& pl) {
+  return (double)pl.g.spec_elems * spec_elem_bytes(pl.prec);
+}
+static double fft_flops(const Plan& pl) {
+  // complex FFT of length Nt on NA/2 packed pairs: 5 (Nt/2... ) -> 5 N log2 N per complex column
+  double lg = std::log2((double)pl.g.nt);
+  return 5.0 * pl.g.nt * lg * (pl.g.NA / (double)pl.g.nt) * 0.5;
+}
+static double xform_flops(const Plan& pl) {
+  const Geom& g = pl.g;
+  double rows = (double)g.B * g.F * g.sy;
+  return pl.schur ? 2.0 * rows * (2.0 * g.sx) * (2.0 * g.sx) : 2.0 * (2.0 * rows) * g.sx * g.sx;
+}
+static double sweep_flops(const Plan& pl) {
+  // complex multiply-adds of the coupling sum_{j>k} T_kj w_j: 8 flops each
+  const Geom& g = pl.g;
+  return 8.0 * g.B * g.F * g.sy * 0.5 * (double)g.sx * (g.sx - 1);
+}
+
 static void apply_prec(Plan& pl, int variant, const double* in, const double* bscale, void* out,
                        bool out_f32, int accumulate, hipStream_t s) {
   const SpaceOp& op = pl.op[variant];
-  { Timed t(pl, PD_STAGE_FFT_FWD, s); fft_time_forward(pl, in, bscale, pl.spec_a, variant, s); }
+  const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
+  const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
+  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, pl.spec_a, variant, s); }
   if (pl.p.dim == 2) {
-    { Timed t(pl, PD_STAGE_XFORM_FWD, s); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
+    { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
     {
-      Timed t(pl, PD_STAGE_LINE_SOLVE, s);
+      Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, pl.schur ? sweep_flops(pl) : 0.0);
       if (pl.schur) schur_sweep(pl, op, pl.spec_b, s);
       else line_solve(pl, op, pl.spec_b, s);
     }
-    { Timed t(pl, PD_STAGE_XFORM_INV, s); xform(pl, op, false, pl.spec_b, pl.spec_a, s); }
+    { Timed t(pl, PD_STAGE_XFORM_INV, s, 2 * sb, xform_flops(pl)); xform(pl, op, false, pl.spec_b, pl.spec_a, s); }
   } else {
-    Timed t(pl, PD_STAGE_LINE_SOLVE, s);
+    Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, 0.0);
     line_solve(pl, op, pl.spec_a, s);
   }
-  { Timed t(pl, PD_STAGE_FFT_INV, s); fft_time_inverse(pl, pl.spec_a, out, out_f32, accumulate, variant, s); }
+  { Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, fft_flops(pl)); fft_time_inverse(pl, pl.spec_a, out, out_f32, accumulate, variant, s); }
 }
 
 static void apply_A(Plan& pl, int variant, const void* u, bool u_f32, const double* b, double* y,
                     hipStream_t s) {
-  Timed t(pl, PD_STAGE_MATVEC, s);
+  const double n = (double)pl.g.NA;
+  Timed t(pl, PD_STAGE_MATVEC, s, n * ((u_f32 ? 4.0 : 8.0) + 8.0 + (b ? 8.0 : 0.0)),
+          n * (pl.L == 3 ? 22.0 : 18.0));
   matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s);
 }
 
@@ -304,9 +341,29 @@ Small carve_small(Plan& pl, char*& p) {
 // Reduction kernels take sigma per slot; slots >= nscale use 1.  We keep a
 // device vector of ones at the tail of sigma for that purpose by launching the
 // reduction with sigma == nullptr for unscaled sums.
+void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s);
+}  // namespace
+static void timed_dot(Plan& pl, const double* V, int64_t vs, int nv, const double* w, double* part,
+                      hipStream_t s) {
+  const double n = (double)pl.g.NA;
+  Timed t(pl, PD_STAGE_DOT, s, n * 8.0 * (nv + (V == w ? 0 : 1)), 2.0 * n * nv);
+  multi_dot(pl, V, vs, nv, w, part, s);
+}
+static void timed_update(Plan& pl, const double* V, int64_t vs, int nv, const double* coef, double* w,
+                         double* part, int dots, hipStream_t s) {
+  const double n = (double)pl.g.NA;
+  Timed t(pl, PD_STAGE_UPDATE, s, n * 8.0 * (nv + 2), n * (2.0 * nv + (dots ? 2.0 * nv + 2.0 : 0.0)));
+  update_dot(pl, V, vs, nv, coef, w, part, dots, s);
+}
+static void timed_reduce(Plan& pl, const double* part, int nv, const double* sigma, int nscaled,
+                         double* h, double* coef, hipStream_t s) {
+  Timed t(pl, PD_STAGE_OTHER, s);
+  reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s);
+}
+namespace {
 void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s) {
-  multi_dot(pl, v, 0, 1, v, sm.partial, s);
-  reduce_partials(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s);
+  timed_dot(pl, v, 0, 1, v, sm.partial, s);
+  timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s);
   std::vector<double> tmp((size_t)pl.g.B * MAXV);
   hipMemcpyAsync(tmp.data(), sm.nrm, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost, s);
   hipStreamSynchronize(s);
@@ -342,7 +399,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   const size_t zb = zf32 ? 4 : 8;
   Small sm = carve_small(pl, p);
   std::vector<double> bn;
-  { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, b, sm, bn, s); }
+  norms(pl, b, sm, bn, s);
   for (int i = 0; i < B; ++i)
     if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
   std::vector<int> it_rhs(B, 0);
@@ -387,7 +444,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     std::vector<double> nr;
     double* rv = (double*)p;
     apply_A(pl, variant, u, false, b, rv, s);
-    { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, rv, sm, nr, s); }
+    norms(pl, rv, sm, nr, s);
     rel(nr);
     push_hist(*std::max_element(res.begin(), res.end()));
     return finish(true);
@@ -399,7 +456,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     std::vector<double> nr;
     while (true) {
       apply_A(pl, variant, u, false, b, r, s);
-      { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, r, sm, nr, s); }
+      norms(pl, r, sm, nr, s);
       bool all = rel(nr);
       for (int i = 0; i < B; ++i)
         if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
@@ -433,7 +490,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     if (first && !o->use_x0) copy_vec(b, Vj(0), g.NA, s);
     else apply_A(pl, variant, u, false, b, Vj(0), s);
     first = false;
-    { Timed t(pl, PD_STAGE_ORTHO, s); norms(pl, Vj(0), sm, nr, s); }
+    norms(pl, Vj(0), sm, nr, s);
     bool all = rel(nr);
     for (int i = 0; i < B; ++i)
       if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
@@ -458,15 +515,14 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       apply_prec(pl, variant, Vj(j), sm.y, Zj(j), zf32, 0, s);
       apply_A(pl, variant, Zj(j), zf32, nullptr, Vj(j + 1), s);
       {
-        Timed t(pl, PD_STAGE_ORTHO, s);
         double* w = Vj(j + 1);
         // classical Gram-Schmidt, two passes; the second pass's dots come from the
         // first pass's update kernel, the final norm by Pythagoras
-        multi_dot(pl, V, vs, j + 1, w, sm.partial, s);
-        reduce_partials(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
-        update_dot(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
-        reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
-        update_dot(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
+        timed_dot(pl, V, vs, j + 1, w, sm.partial, s);
+        timed_reduce(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
+        timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
+        timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
+        timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
         hipMemcpyAsync(hbuf.data(), sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(hbuf.data() + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
                        hipMemcpyDeviceToHost, s);
@@ -537,7 +593,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     }
     if (kmax > 0) {
       hipMemcpyAsync(sm.y, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s);
-      Timed t(pl, PD_STAGE_OTHER, s);
+      Timed t(pl, PD_STAGE_OTHER, s, (double)g.NA * (16.0 + kmax * (double)zb), 2.0 * g.NA * kmax);
       x_update(pl, Z, zf32, zs, kmax, sm.y, u, s);
     }
   }
@@ -691,11 +747,30 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
         fill(gf, [&](int k, int j) { return std::conj(op.Q[(size_t)k * n + j]); });
         fill(gi, [&](int k, int j) { return op.Q[(size_t)j * n + k]; });
       }
-      op.g_fwd = take(gf.size() * ce);
-      op.g_inv = take(gi.size() * ce);
-      if (pl->prec == Prec::F64) { store_compute<double>((void*)op.g_fwd, gf, s, keep); store_compute<double>((void*)op.g_inv, gi, s, keep); }
-      else if (pl->prec == Prec::F32) { store_compute<float>((void*)op.g_fwd, gf, s, keep); store_compute<float>((void*)op.g_inv, gi, s, keep); }
-      else { store_compute<Bf16Bits>((void*)op.g_fwd, gf, s, keep); store_compute<Bf16Bits>((void*)op.g_inv, gi, s, keep); }
+      (void)ce;
+      op.g_fwd = take(gemm_matrix_bytes(pl->prec, gf.size()));
+      op.g_inv = take(gemm_matrix_bytes(pl->prec, gi.size()));
+      for (int w = 0; w < 2; ++w) {
+        void* dst = (void*)(w ? op.g_inv : op.g_fwd);
+        const std::vector<double>& src = w ? gi : gf;
+        if (pl->prec == Prec::F64) store_compute<double>(dst, src, s, keep);
+        else if (pl->prec == Prec::F32) store_compute<float>(dst, src, s, keep);
+        else if (pl->prec == Prec::BF16X1) store_compute<Bf16Bits>(dst, src, s, keep);
+        else {
+          // hi part, lo part (residual of the hi rounding), float32 copy
+          std::vector<double> hi(src.size()), lo(src.size());
+          for (size_t i = 0; i < src.size(); ++i) {
+            uint32_t u = (uint32_t)to_bf16_bits(src[i]) << 16;
+            float h;
+            std::memcpy(&h, &u, 4);
+            hi[i] = h;
+            lo[i] = (double)((float)src[i] - h);
+          }
+          store_compute<Bf16Bits>(dst, hi, s, keep);
+          store_compute<Bf16Bits>((char*)dst + 2 * src.size(), lo, s, keep);
+          store_compute<float>((char*)dst + 4 * src.size(), src, s, keep);
+        }
+      }
       if (pl->schur) {
         std::vector<double> tp(2 * (size_t)n * n);
         for (size_t i = 0; i < (size_t)n * n; ++i) { tp[i] = op.Tm[i].real(); tp[(size_t)n * n + i] = op.Tm[i].imag(); }
@@ -834,14 +909,16 @@ paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable) {
 }
 
 paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,
-                                         int32_t reset) {
+                                         double* bytes, double* flops, int32_t reset) {
   Plan* pl = reinterpret_cast<Plan*>(plan);
   if (!pl) { set_error("plan is NULL"); return PD_ERR_INVALID; }
   drain_timer(*pl);
   for (int i = 0; i < PD_NUM_STAGES; ++i) {
     if (ms) ms[i] = pl->timer.ms[i];
     if (counts) counts[i] = pl->timer.count[i];
-    if (reset) { pl->timer.ms[i] = 0; pl->timer.count[i] = 0; }
+    if (bytes) bytes[i] = pl->timer.bytes[i];
+    if (flops) flops[i] = pl->timer.flops[i];
+    if (reset) { pl->timer.ms[i] = 0; pl->timer.count[i] = 0; pl->timer.bytes[i] = 0; pl->timer.flops[i] = 0; }
   }
   return check_hip("stage times");
 }

@@ -17,7 +17,8 @@ using cd = std::complex<double>;
 bool complex_schur(int n, std::vector<cd>& h, std::vector<cd>& q);
 
 // Numeric formats of the preconditioner.
-enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+// BF16: split hi+lo product (3 bf16 MFMAs); BF16X1: single bf16 product.
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X1 = 3 };
 
 // Geometry of the spectral buffer [batch][F][sy][2][sx]: F = nt/2 + 1
 // frequencies, each slice a sy x sx complex field stored row-planar (a row
@@ -59,6 +60,8 @@ struct StageTimer {
   std::vector<hipEvent_t> pool;
   double ms[PD_NUM_STAGES] = {0};
   int64_t count[PD_NUM_STAGES] = {0};
+  double bytes[PD_NUM_STAGES] = {0};
+  double flops[PD_NUM_STAGES] = {0};
 };
 
 struct Plan {
@@ -112,6 +115,7 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
            hipStream_t s);
 void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
+size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
 // all-at-once operator
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s);

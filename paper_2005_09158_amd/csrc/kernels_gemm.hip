@@ -172,6 +172,142 @@ void launch_gemm(const Ts* A, const Tc* Bt, Ts* C, int64_t M, int N, int K, hipS
   k_gemm<Ts, Tc, BM, BN, BK><<<dim3((unsigned)blocks), NT, 0, s>>>(A, Bt, C, M, N, K, ntn);
 }
 
+// bf16 MFMA path for float32 rows (K % 32 == 0): float4 row loads, the rows
+// rounded to bf16 on the way into LDS, 16-byte fragment reads, the next k-tile
+// prefetched into registers while the current one is multiplied.  SPLIT = 3
+// keeps float32-level accuracy with bf16 instructions: a = a_hi + a_lo and
+// b = b_hi + b_lo (each bf16), a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, the
+// dropped a_lo b_lo term being 2^-16 relative.  SPLIT = 1 is the plain
+// single bf16 product.  Bt holds b_hi ([N][K]) followed by b_lo.
+// Tiles: 128 x 128 x 32, 2 x 2 waves of 64 x 64 (4 x 4 blocks of 16 x 16).
+// Blocks are ordered so that the N-tiles sharing one row block of A run on
+// the same XCD (consecutive workgroup ids are dealt round-robin to the 8
+// XCDs, each with its own L2).
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) {
+  __bf16 h = (__bf16)v;
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __builtin_bit_cast(float, (unsigned int)b << 16);
+}
+
+template <int SPLIT>
+__global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
+                                                  const unsigned short* __restrict__ Bt,
+                                                  float* __restrict__ C, int64_t M, int N, int K,
+                                                  int ntn, int64_t nblocks) {
+  constexpr int BM = 128, BN = 128, BK = 32, LD = BK + 8;   // LDS row: 80 bytes
+  constexpr int NA = (SPLIT == 3) ? 2 : 1;
+  __shared__ __align__(16) unsigned short As[NA][BM * LD];
+  __shared__ __align__(16) unsigned short Bs[NA][BN * LD];
+
+  int64_t bid = blockIdx.x;
+  if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);   // XCD-aware order
+  const int tn = (int)(bid % ntn);
+  const int64_t tm = bid / ntn;
+  const int64_t m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const unsigned short* Blo = Bt + (int64_t)N * K;
+
+  // per-thread staging: A 4 x float4 (rows tid/8 + 32 i, k = 4 (tid%8)),
+  // B 2 x 16 bytes per part (rows tid/4 + 64 i, k = 8 (tid%4))
+  float4 ra[4];
+  uint4 rb[NA][2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int64_t gm = m0 + (tid >> 3) + 32 * i;
+      ra[i] = (gm < M) ? *reinterpret_cast<const float4*>(A + gm * K + k0 + 4 * (tid & 7))
+                       : float4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int gn = n0 + (tid >> 2) + 64 * i;
+      int64_t off = (int64_t)gn * K + k0 + 8 * (tid & 3);
+      rb[0][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Bt + off) : uint4{0, 0, 0, 0};
+      if constexpr (NA == 2) rb[1][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Blo + off) : uint4{0, 0, 0, 0};
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int r = (tid >> 3) + 32 * i, c = 4 * (tid & 7);
+      float v[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+      us4 hi, lo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hi[q] = bf16_bits(v[q]);
+        if constexpr (NA == 2) lo[q] = bf16_bits(v[q] - bf16_val(hi[q]));
+      }
+      *reinterpret_cast<us4*>(&As[0][r * LD + c]) = hi;
+      if constexpr (NA == 2) *reinterpret_cast<us4*>(&As[1][r * LD + c]) = lo;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a][r * LD + c]) = rb[a][i];
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
+    bf8 a[NA][4], b[NA][4];
+#pragma unroll
+    for (int x = 0; x < NA; ++x) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[x][i] = *reinterpret_cast<const bf8*>(&As[x][(wm0 + 16 * i + lr) * LD + 8 * lk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x][(wn0 + 16 * j + lr) * LD + 8 * lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        if constexpr (NA == 2) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int64_t gm = m0 + wm0 + 16 * i + 4 * lk + v;
+        int gn = n0 + wn0 + 16 * j + lr;
+        if (gm < M && gn < N) C[gm * N + gn] = acc[i][j][v];
+      }
+}
+
+template <int SPLIT>
+void launch_gemm_bf16(const float* A, const unsigned short* Bt, float* C, int64_t M, int N, int K,
+                      hipStream_t s) {
+  int ntn = (N + 127) / 128;
+  int64_t nblocks = ((M + 127) / 128) * ntn;
+  k_gemm_bf16<SPLIT><<<dim3((unsigned)nblocks), NT, 0, s>>>(A, Bt, C, M, N, K, ntn, nblocks);
+}
+
 }  // namespace
 
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
@@ -196,8 +332,21 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
       launch_gemm<float, float, 64, 64, 16>((const float*)in, (const float*)Bt, (float*)out, M, N, K, s);
       break;
     case Prec::BF16:
-      launch_gemm<float, __bf16, 128, 128, 32>((const float*)in, (const __bf16*)Bt, (float*)out, M, N, K, s);
+    case Prec::BF16X1: {
+      const bool split = pl.prec == Prec::BF16;
+      if (K % 32 == 0) {
+        if (split) launch_gemm_bf16<3>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s);
+        else launch_gemm_bf16<1>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s);
+      } else if (split) {
+        // ragged K (nx not a multiple of 16): the float32 MFMA kernel on the float32
+        // copy of the matrix that follows the two bf16 parts
+        const float* B32 = (const float*)((const unsigned short*)Bt + (size_t)2 * N * K);
+        launch_gemm<float, float, 64, 64, 16>((const float*)in, B32, (float*)out, M, N, K, s);
+      } else {
+        launch_gemm<float, __bf16, 128, 128, 32>((const float*)in, (const __bf16*)Bt, (float*)out, M, N, K, s);
+      }
       break;
+    }
   }
 }
 

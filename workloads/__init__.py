@@ -12,6 +12,8 @@ from .fields import (  # noqa: F401
     initial_state,
     initial_velocity,
     source_term,
+    source_term_torch,
+    source_factors,
     tracking_target,
     fd_directions,
     random_vector,
