@@ -170,28 +170,39 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
+// Multi-dot and update kernels, templated on the number of Krylov vectors
+// (NV <= 8; larger counts use the generic predicated form).  Each thread
+// handles pairs of consecutive doubles (16-byte loads); a workgroup owns one
+// contiguous chunk of one right-hand side.
+
 // partial[b][chunk][i] = sum over the chunk of V_i[b] . w[b]  (i < nv)
-__global__ __launch_bounds__(NT) void k_mdot(const double* __restrict__ V, int64_t vstride, int nv,
-                                             const double* __restrict__ w, double* __restrict__ partial,
-                                             int64_t N1, int chunks) {
+template <int NV>
+__global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int64_t vstride, int nv,
+                                               const double* __restrict__ w, double* __restrict__ partial,
+                                               int64_t N1, int chunks) {
   __shared__ double red[4];
+  constexpr int NR = NV > 0 ? NV : MAXV;
   const int b = blockIdx.y, c = blockIdx.x;
-  const int64_t per = (N1 + chunks - 1) / chunks;
+  const int64_t per = ((N1 + chunks - 1) / chunks + 1) & ~(int64_t)1;
   const int64_t beg = c * per, end = min(N1, beg + per);
   const double* wb = w + (int64_t)b * N1;
-  double acc[MAXV];
+  const double* Vb = V + (int64_t)b * N1;
+  double acc[NR];
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) acc[i] = 0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
-    double wv = wb[e];
+  for (int i = 0; i < NR; ++i) acc[i] = 0;
+  for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
+    double2 wv = *reinterpret_cast<const double2*>(wb + e);
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < nv) acc[i] += V[i * vstride + (int64_t)b * N1 + e] * wv;
+    for (int i = 0; i < NR; ++i)
+      if (NV > 0 || i < nv) {
+        double2 v = *reinterpret_cast<const double2*>(Vb + i * vstride + e);
+        acc[i] += v.x * wv.x + v.y * wv.y;
+      }
   }
   double* out = partial + ((int64_t)b * chunks + c) * MAXV;
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    if (i < nv) {  // nv is uniform: the barrier inside is reached by all threads
+  for (int i = 0; i < NR; ++i) {
+    if (NV > 0 || i < nv) {  // nv is uniform: the barrier inside is reached by all threads
       double t = block_sum(acc[i], red);
       if (threadIdx.x == 0) out[i] = t;
     }
@@ -218,48 +229,52 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partia
 
 // w[b] -= sum_i coef[b][i] V_i[b]; optionally partial dots of the new w with
 // V_i (slots 0..nv-1) and with itself (slot nv).
-__global__ __launch_bounds__(NT) void k_update(const double* __restrict__ V, int64_t vstride, int nv,
-                                               const double* __restrict__ coef, int ldc,
-                                               double* __restrict__ w, double* __restrict__ partial,
-                                               int64_t N1, int chunks, int want_dots) {
+template <int NV, bool DOTS>
+__global__ __launch_bounds__(NT) void k_update_t(const double* __restrict__ V, int64_t vstride, int nv,
+                                                 const double* __restrict__ coef, int ldc,
+                                                 double* __restrict__ w, double* __restrict__ partial,
+                                                 int64_t N1, int chunks) {
   __shared__ double red[4];
+  constexpr int NR = NV > 0 ? NV : MAXV;
   const int b = blockIdx.y, c = blockIdx.x;
-  const int64_t per = (N1 + chunks - 1) / chunks;
+  const int64_t per = ((N1 + chunks - 1) / chunks + 1) & ~(int64_t)1;
   const int64_t beg = c * per, end = min(N1, beg + per);
   double* wb = w + (int64_t)b * N1;
-  double cf[MAXV];
+  const double* Vb = V + (int64_t)b * N1;
+  double cf[NR];
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) cf[i] = (i < nv) ? coef[b * ldc + i] : 0.0;
-  double acc[MAXV + 1];
+  for (int i = 0; i < NR; ++i) cf[i] = (NV > 0 || i < nv) ? coef[b * ldc + i] : 0.0;
+  double acc[NR + 1];
 #pragma unroll
-  for (int i = 0; i <= MAXV; ++i) acc[i] = 0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
-    double vv[MAXV];
-    double wv = wb[e];
+  for (int i = 0; i <= NR; ++i) acc[i] = 0;
+  for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
+    double2 vv[NR];
+    double2 wv = *reinterpret_cast<const double2*>(wb + e);
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < nv) {
-        vv[i] = V[i * vstride + (int64_t)b * N1 + e];
-        wv -= cf[i] * vv[i];
+    for (int i = 0; i < NR; ++i)
+      if (NV > 0 || i < nv) {
+        vv[i] = *reinterpret_cast<const double2*>(Vb + i * vstride + e);
+        wv.x -= cf[i] * vv[i].x;
+        wv.y -= cf[i] * vv[i].y;
       }
-    wb[e] = wv;
-    if (want_dots) {
+    *reinterpret_cast<double2*>(wb + e) = wv;
+    if (DOTS) {
 #pragma unroll
-      for (int i = 0; i < MAXV; ++i)
-        if (i < nv) acc[i] += vv[i] * wv;
-      acc[MAXV] += wv * wv;
+      for (int i = 0; i < NR; ++i)
+        if (NV > 0 || i < nv) acc[i] += vv[i].x * wv.x + vv[i].y * wv.y;
+      acc[NR] += wv.x * wv.x + wv.y * wv.y;
     }
   }
-  if (!want_dots) return;
+  if (!DOTS) return;
   double* out = partial + ((int64_t)b * chunks + c) * MAXV;
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    if (i < nv) {
+  for (int i = 0; i < NR; ++i) {
+    if (NV > 0 || i < nv) {
       double t = block_sum(acc[i], red);
       if (threadIdx.x == 0) out[i] = t;
     }
   }
-  double t = block_sum(acc[MAXV], red);
+  double t = block_sum(acc[NR], red);
   if (threadIdx.x == 0) out[nv] = t;
 }
 
@@ -332,7 +347,8 @@ void rhs_transpose(const Plan& pl, const double* lam, double* gU0, double* gu1, 
 }
 
 int dot_chunks(const Plan& pl) {
-  int64_t c = pl.g.N1 / (NT * 64);
+  // about 16 pairs per thread per chunk, at most 2048 chunks per right-hand side
+  int64_t c = pl.g.N1 / (NT * 32);
   if (c < 1) c = 1;
   if (c > 2048) c = 2048;
   return (int)c;
@@ -341,7 +357,13 @@ int dot_chunks(const Plan& pl) {
 void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* w,
                double* partial, hipStream_t s) {
   int chunks = dot_chunks(pl);
-  k_mdot<<<dim3(chunks, pl.g.B), NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks);
+  dim3 grid(chunks, pl.g.B);
+  switch (nv) {
+#define PD_MD(K) case K: k_mdot_t<K><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks); return;
+    PD_MD(1) PD_MD(2) PD_MD(3) PD_MD(4) PD_MD(5) PD_MD(6) PD_MD(7) PD_MD(8)
+#undef PD_MD
+    default: k_mdot_t<0><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks);
+  }
 }
 
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
@@ -353,8 +375,19 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
                 double* w, double* partial, int want_dots, hipStream_t s) {
   int chunks = dot_chunks(pl);
-  k_update<<<dim3(chunks, pl.g.B), NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1,
-                                               chunks, want_dots);
+  dim3 grid(chunks, pl.g.B);
+#define PD_UP(K)                                                                                  \
+  case K:                                                                                         \
+    if (want_dots) k_update_t<K, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks); \
+    else k_update_t<K, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks); \
+    return;
+  switch (nv) {
+    PD_UP(1) PD_UP(2) PD_UP(3) PD_UP(4) PD_UP(5) PD_UP(6) PD_UP(7) PD_UP(8)
+    default:
+      if (want_dots) k_update_t<0, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks);
+      else k_update_t<0, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks);
+  }
+#undef PD_UP
 }
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
