@@ -202,6 +202,7 @@ size_t tables_bytes(const Plan& pl) {
       b += align_up(sizeof(double2) * n);                             // tk
       b += 2 * align_up(gemm_matrix_bytes(pl.prec, gm));              // g_fwd, g_inv
       if (pl.schur) b += align_up(2 * n * n * spec_elem_bytes(pl.prec));  // T (line precision)
+      if (pl.schur) b += align_up((size_t)2 * g.F * n * g.sy * spec_elem_bytes(pl.prec));  // line LU
     }
   }
   b += 2 * align_up((size_t)g.spec_elems * spec_elem_bytes(pl.prec));
@@ -777,11 +778,16 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
         op.tup = take(tp.size() * spec_elem_bytes(pl->prec));
         if (pl->prec == Prec::F64) store_compute<double>((void*)op.tup, tp, s, keep);
         else store_compute<float>((void*)op.tup, tp, s, keep);
+        op.lu = take((size_t)2 * g.F * n * g.sy * spec_elem_bytes(pl->prec));
       } else {
         op.tup = nullptr;
+        op.lu = nullptr;
       }
     }
   }
+  // line factorisations of the back-sweep (both operators), once per binding
+  if (pl->p.dim == 2 && pl->schur)
+    for (int v = 0; v < 2; ++v) schur_line_lu(*pl, pl->op[v], s);
   pl->spec_a = take((size_t)g.spec_elems * spec_elem_bytes(pl->prec));
   pl->spec_b = take((size_t)g.spec_elems * spec_elem_bytes(pl->prec));
   pl->solver_base = p;

@@ -47,6 +47,7 @@ struct SpaceOp {
   const void* g_fwd = nullptr;  // S -> S * conj(Q)
   const void* g_inv = nullptr;  // W -> W * Q^T
   const void* tup = nullptr;    // Schur T (planar re/im, [2][nx][nx], compute format); null if diagonal
+  void* lu = nullptr;           // Schur path: inverse LU pivots of every line, [F][nx][ny] complex
   // host copies
   std::vector<cd> Q, Tm;        // nx*nx complex (row-major): K_x = Q T Q^H
 };
@@ -116,6 +117,7 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
 void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
+void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu
 // all-at-once operator
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s);

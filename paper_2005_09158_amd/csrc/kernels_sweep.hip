@@ -52,10 +52,79 @@ template <> struct SweepMfma<double> {
 
 // NB: modes per block; BK: k-chunk of the coupling product; RB: 16-row MFMA
 // blocks per wave (the four waves cover 64 RB rows >= ny).
-template <typename T, int R, int P, int NB, int BK, int RB>
+template <typename T> struct V4;
+template <> struct V4<float> { using t = float4; };
+template <> struct V4<double> { using t = double4; };
+
+// Coupling product with fragments loaded straight from global memory
+// (sx % 4 == 0).  Within each block of 16 consecutive solved modes j, lane
+// group g = lane/16 owns j0 + 4g .. j0 + 4g + 3 and feeds element s of its
+// four-vector to MFMA step s: the k order inside the block is permuted, the
+// same way for A (W rows) and B (T rows), which leaves the sum unchanged.
+// Each wave covers its own RB x 16 rows; T rows are shared through the cache.
+template <typename T, int NB, int RB>
+__device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, const T* tim, int sx,
+                                                int sy, int k0, int nk, int kend, int wave, int lr,
+                                                int lk, typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+  using MF = SweepMfma<T>;
+  using Q4 = typename V4<T>::t;
+  constexpr int NCB = 2 * NB / 16;
+  const int q = (NCB == 2) ? lr : (lr & 7);          // mode of this lane's output column
+  const int part = (NCB == 2) ? 0 : (lr >> 3);       // NB = 8: lanes 8..15 hold imaginary parts
+  const bool qok = q < nk;
+  const T* trow = tre + (int64_t)(k0 + q) * sx;
+  const T* irow = tim + (int64_t)(k0 + q) * sx;
+  const int r0 = wave * RB * 16 + lr;
+  for (int j0 = kend; j0 < sx; j0 += 16) {
+    const int j = j0 + 4 * lk;
+    const bool jok = j < sx;
+    Q4 tr{}, ti{};
+    if (qok && jok) {
+      tr = *reinterpret_cast<const Q4*>(trow + j);
+      ti = *reinterpret_cast<const Q4*>(irow + j);
+    }
+    Q4 ar[RB], ai[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = r0 + 16 * i;
+      if (jok && r < sy) {
+        const T* row = slice + (int64_t)r * 2 * sx;
+        ar[i] = *reinterpret_cast<const Q4*>(row + j);
+        ai[i] = *reinterpret_cast<const Q4*>(row + sx + j);
+      } else {
+        ar[i] = Q4{};
+        ai[i] = Q4{};
+      }
+    }
+    const T trv[4] = {tr.x, tr.y, tr.z, tr.w}, tiv[4] = {ti.x, ti.y, ti.z, ti.w};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      // real block form: out_re += Wr Tr - Wi Ti ; out_im += Wr Ti + Wi Tr
+      T b_re_r, b_re_i, b_im_r, b_im_i;   // B for (re input, im input) x (re out, im out)
+      b_re_r = trv[st]; b_re_i = -tiv[st]; b_im_r = tiv[st]; b_im_i = trv[st];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const T av_r = (st == 0) ? ar[i].x : (st == 1) ? ar[i].y : (st == 2) ? ar[i].z : ar[i].w;
+        const T av_i = (st == 0) ? ai[i].x : (st == 1) ? ai[i].y : (st == 2) ? ai[i].z : ai[i].w;
+        if constexpr (NCB == 2) {
+          acc[i][0] = MF::run(av_r, b_re_r, acc[i][0]);
+          acc[i][0] = MF::run(av_i, b_re_i, acc[i][0]);
+          acc[i][1] = MF::run(av_r, b_im_r, acc[i][1]);
+          acc[i][1] = MF::run(av_i, b_im_i, acc[i][1]);
+        } else {
+          acc[i][0] = MF::run(av_r, part ? b_im_r : b_re_r, acc[i][0]);
+          acc[i][0] = MF::run(av_i, part ? b_im_i : b_re_i, acc[i][0]);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int R, int P, int NB, int BK, int RB, bool VEC>
 __global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                     const double2* __restrict__ tk,
-                                                    const T* __restrict__ tup, double lo, double di,
+                                                    const T* __restrict__ tup,
+                                                    const T* __restrict__ lu, double lo, double di,
                                                     double up, int F, int sx, int sy, int ldy) {
   static_assert(2 * NB <= BK + 1, "the product staging area also holds C");
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
@@ -67,9 +136,9 @@ __global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, con
   extern __shared__ __align__(16) unsigned char smraw[];
   T* sre = reinterpret_cast<T*>(smraw);
   T* sim = sre + NB * ldy;
-  T* As = sim + NB * ldy;                // [NYP][LDA]; after the K loop: C[NYP][LDA]
-  T* Bs = As + NYP * LDA;                // [2 NB][LDA]
-  T* Tb = Bs + 2 * NB * LDA;             // block of T: [2][NB][NB] (re, im)
+  T* As = sim + NB * ldy;                // [NYP][LDA]; after the K loop: C[NYP][LDA] (staged path)
+  T* Bs = As + (VEC ? 0 : NYP * LDA);    // [2 NB][LDA] (staged path)
+  T* Tb = Bs + (VEC ? 0 : 2 * NB * LDA); // block of T: [2][NB][NB] (re, im)
   T* Sb = Tb + 2 * NB * NB;              // per-mode diagonal coefficient b_q: [2][NB]
 
   const int n = blockIdx.x, b = blockIdx.y;
@@ -101,7 +170,39 @@ __global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, con
       Sb[tid] = (T)(l1.x + l2.x * shr - l2.y * shi);
       Sb[NB + tid] = (T)(l1.y + l2.x * shi + l2.y * shr);
     }
-    if (J > 0) {
+    if (VEC && J > 0) {
+      typename MF::acc_t acc[RB][NCB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+      coupling_direct<T, NB, RB>(slice, tre, tim, sx, sy, k0, nk, kend, wave, lr, lk, acc);
+      __syncthreads();   // the tile is complete before the subtraction
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = wave * RB * 16 + i * 16 + MF::row(lk, v);
+          T cr, ci;
+          int q;
+          if constexpr (NCB == 2) {
+            cr = acc[i][0][v];
+            ci = acc[i][1][v];
+            q = lr;
+          } else {
+            cr = acc[i][0][v];
+            ci = __shfl_down(acc[i][0][v], 8, 16);   // imaginary part from lane lr + 8
+            q = lr;
+          }
+          if (y < sy && q < nk && (NCB == 2 || lr < 8)) {
+            int idx = lidx(q, y, ldy, R);
+            sre[idx] -= l2r * cr - l2i * ci;
+            sim[idx] -= l2r * ci + l2i * cr;
+          }
+        }
+    } else if (!VEC && J > 0) {
       typename MF::acc_t acc[RB][NCB];
 #pragma unroll
       for (int i = 0; i < RB; ++i)
@@ -179,35 +280,51 @@ __global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, con
     }
     __syncthreads();
     if (wave == 0) {
+      // Lines of the block in order, each with its precomputed LU (inverse
+      // pivots of line (n, k) at lu[((n sx + k) sy + y)], complex) and the
+      // coupling to the block's already solved lines gathered left-looking
+      // from LDS: r_q -= lambda2 sum_{q' > q} T[k0+q][k0+q'] w_q'.
       const bool active = (seg == 0);
       const Cx<T> ca = active ? Cx<T>{(T)(l2.x * lo), (T)(l2.y * lo)} : cz<T>();
       const Cx<T> cc = active ? Cx<T>{(T)(l2.x * up), (T)(l2.y * up)} : cz<T>();
+      const T* lun = lu + (int64_t)n * sx * sy * 2;
+      Cx<T> ivn[R];
+      auto load_inv = [&](int q, Cx<T> (&iv)[R]) {
+        const T* src = lun + ((int64_t)(k0 + q) * sy + p * R) * 2;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
+      };
+      if (nk > 0) load_inv(nk - 1, ivn);
       for (int q = nk - 1; q >= 0; --q) {
-        Cx<T> cb = active ? Cx<T>{Sb[q], Sb[NB + q]} : c1<T>();
+        Cx<T> iv[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) iv[i] = ivn[i];
+        if (q > 0) load_inv(q - 1, ivn);     // next line's pivots in flight
         Cx<T> d[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           int idx = q * ldy + p * (R + 1) + i;
           d[i] = active ? Cx<T>{sre[idx], sim[idx]} : cz<T>();
         }
-        tri_wave<T, R, P>(d, ca, cb, cc, sy, p);
+        for (int qq = q + 1; qq < nk; ++qq) {
+          T tr = Tb[q * NB + qq], ti = Tb[NB * NB + q * NB + qq];
+          T cr = l2r * tr - l2i * ti, ci = l2r * ti + l2i * tr;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            int idx = qq * ldy + p * (R + 1) + i;
+            T wr = sre[idx], wi = sim[idx];
+            d[i].x -= cr * wr - ci * wi;
+            d[i].y -= cr * wi + ci * wr;
+          }
+        }
+        lu_scan_wave<T, R, P>(d, iv, ca, cc, sy, p);
         if (active) {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             int idx = q * ldy + p * (R + 1) + i;
             sre[idx] = d[i].x;
             sim[idx] = d[i].y;
-          }
-          // columns q' < q of the block: r_q' -= lambda2 T[k0+q'][k0+q] w_q
-          for (int qq = 0; qq < q; ++qq) {
-            T tr = Tb[qq * NB + q], ti = Tb[NB * NB + qq * NB + q];
-            T cr = l2r * tr - l2i * ti, ci = l2r * ti + l2i * tr;
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-              int idx = qq * ldy + p * (R + 1) + i;
-              sre[idx] -= cr * d[i].x - ci * d[i].y;
-              sim[idx] -= cr * d[i].y + ci * d[i].x;
-            }
           }
         }
       }
@@ -218,7 +335,39 @@ __global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, con
   }
 }
 
-struct SweepShape { int R, P, RB, ldy; size_t lds; };
+
+// Inverse pivots of the non-pivoted LU factorisation of every line matrix
+// [(lambda1_n + lambda2_n T_kk) I + lambda2_n K_y] (float64 recurrence,
+// stored in the working precision): one thread per (frequency, mode).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_line_lu(T* __restrict__ lu, const double2* __restrict__ lam,
+                                                const double2* __restrict__ tk, double lo, double di,
+                                                double up, int F, int sx, int sy) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)F * sx) return;
+  const int n = (int)(t / sx), k = (int)(t - (int64_t)n * sx);
+  const double2 l1 = lam[n], l2 = lam[F + n], tt = tk[k];
+  const double shr = tt.x + di, shi = tt.y;
+  const double br = l1.x + l2.x * shr - l2.y * shi, bi = l1.y + l2.x * shi + l2.y * shr;
+  // a c = lambda2^2 lo up
+  const double acr = (l2.x * l2.x - l2.y * l2.y) * lo * up, aci = 2.0 * l2.x * l2.y * lo * up;
+  T* out = lu + t * sy * 2;
+  double ir = 0, ii = 0;
+  for (int y = 0; y < sy; ++y) {
+    double mr = br, mi = bi;
+    if (y > 0) {  // m = b - a c / m_prev = b - (a c) inv_prev
+      mr -= acr * ir - aci * ii;
+      mi -= acr * ii + aci * ir;
+    }
+    const double den = 1.0 / (mr * mr + mi * mi);
+    ir = mr * den;
+    ii = -mi * den;
+    out[2 * y] = (T)ir;
+    out[2 * y + 1] = (T)ii;
+  }
+}
+
+struct SweepShape { int R, P, RB, ldy; size_t lds; bool vec; };
 
 template <typename T, int NB, int BK>
 SweepShape sweep_shape(const Plan& pl) {
@@ -231,19 +380,20 @@ SweepShape sweep_shape(const Plan& pl) {
   if ((ldy & 1) == 0) ldy += 1;
   int RB = 1;
   while (64 * RB < g.sy) RB <<= 1;
-  size_t lds = sizeof(T) * ((size_t)2 * NB * ldy + (size_t)64 * RB * (BK + 1) + (size_t)2 * NB * (BK + 1) +
-                            (size_t)2 * NB * NB + (size_t)2 * NB);
-  return SweepShape{R, P, RB, ldy, lds};
+  const bool vec = (g.sx % 4) == 0;
+  size_t stage = vec ? 0 : (size_t)64 * RB * (BK + 1) + (size_t)2 * NB * (BK + 1);
+  size_t lds = sizeof(T) * ((size_t)2 * NB * ldy + stage + (size_t)2 * NB * NB + (size_t)2 * NB);
+  return SweepShape{R, P, RB, ldy, lds, vec};
 }
 
 template <typename T, int R, int P, int NB, int BK, int RB>
 void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, BK>(pl);
-  auto kfn = k_schur_sweep<T, R, P, NB, BK, RB>;
+  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, BK, RB, true> : k_schur_sweep<T, R, P, NB, BK, RB, false>;
   hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
-  kfn<<<dim3(g.F, g.B), NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, (const T*)op.tup, op.lo, op.di,
-                                         op.up, g.F, g.sx, g.sy, sh.ldy);
+  kfn<<<dim3(g.F, g.B), NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, (const T*)op.tup, (const T*)op.lu,
+                                         op.lo, op.di, op.up, g.F, g.sx, g.sy, sh.ldy);
 }
 
 // (NB, BK) per precision and row count: wide blocks while the A staging fits
@@ -276,6 +426,16 @@ size_t schur_sweep_lds(const Plan& pl) {
   }
   SweepShape a = sweep_shape<float, 16, 32>(pl);
   return a.RB == 8 ? sweep_shape<float, SweepCfg<float>::NB8, SweepCfg<float>::BK8>(pl).lds : a.lds;
+}
+
+void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {
+  const Geom& g = pl.g;
+  const int64_t lines = (int64_t)g.F * g.sx;
+  dim3 grid((unsigned)((lines + NT - 1) / NT));
+  if (pl.prec == Prec::F64)
+    k_line_lu<double><<<grid, NT, 0, s>>>((double*)op.lu, pl.d_lam, op.tk, op.lo, op.di, op.up, g.F, g.sx, g.sy);
+  else
+    k_line_lu<float><<<grid, NT, 0, s>>>((float*)op.lu, pl.d_lam, op.tk, op.lo, op.di, op.up, g.F, g.sx, g.sy);
 }
 
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {

@@ -168,5 +168,78 @@ __device__ void solve_tile_line(T* sre, T* sim, int k, bool active, Cx<T> a, Cx<
 }
 
 
+// Solve a x_{i-1} + b_i x_i + c x_{i+1} = d_i (i < N) given the inverse pivots
+// inv_i = 1/m_i of its non-pivoted LU factorisation (m_0 = b_0, m_i = b_i -
+// a c / m_{i-1}): the forward and backward substitutions are first-order
+// linear recurrences, evaluated as affine scans across the P lanes of the
+// segment (R rows per lane; rows >= N are identity).  Every lane of the wave
+// must call this (shuffles).
+template <typename T, int R, int P>
+__device__ void lu_scan_wave(Cx<T> (&d)[R], const Cx<T> (&inv)[R], Cx<T> a, Cx<T> c, int N, int p) {
+  const int row0 = p * R;
+  // forward: d'_y = (d_y - a_y d'_{y-1}) inv_y  ->  d'_i = al_i + be_i * (entering d')
+  Cx<T> al[R], be[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int y = row0 + i;
+    const Cx<T> ay = (y > 0 && y < N) ? a : cz<T>();
+    const Cx<T> iv = (y < N) ? inv[i] : c1<T>();
+    const Cx<T> dy = (y < N) ? d[i] : cz<T>();
+    if (i == 0) {
+      al[0] = mul(dy, iv);
+      be[0] = neg(mul(ay, iv));
+    } else {
+      al[i] = mul(sub(dy, mul(ay, al[i - 1])), iv);
+      be[i] = neg(mul(mul(ay, be[i - 1]), iv));
+    }
+  }
+  Cx<T> A = al[R - 1], B = be[R - 1];
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) {
+    Cx<T> Ap = shup(A, o, P), Bp = shup(B, o, P);
+    if (p >= o) {
+      A = Cx<T>{A.x + B.x * Ap.x - B.y * Ap.y, A.y + B.x * Ap.y + B.y * Ap.x};
+      B = mul(B, Bp);
+    }
+  }
+  Cx<T> din = shup(A, 1, P);
+  if (p == 0) din = cz<T>();
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    Cx<T> t = mul(be[i], din);
+    d[i] = Cx<T>{al[i].x + t.x, al[i].y + t.y};
+  }
+  // backward: x_y = d'_y - c'_y x_{y+1}, c'_y = c inv_y (0 on the last row)
+  Cx<T> ga[R], de[R];
+#pragma unroll
+  for (int i = R - 1; i >= 0; --i) {
+    const int y = row0 + i;
+    const Cx<T> cy = (y < N - 1) ? mul(c, inv[i]) : cz<T>();
+    if (i == R - 1) {
+      ga[i] = d[i];
+      de[i] = neg(cy);
+    } else {
+      ga[i] = sub(d[i], mul(cy, ga[i + 1]));
+      de[i] = neg(mul(cy, de[i + 1]));
+    }
+  }
+  Cx<T> G = ga[0], D = de[0];
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) {
+    Cx<T> Gn = shdn(G, o, P), Dn = shdn(D, o, P);
+    if (p + o < P) {
+      G = Cx<T>{G.x + D.x * Gn.x - D.y * Gn.y, G.y + D.x * Gn.y + D.y * Gn.x};
+      D = mul(D, Dn);
+    }
+  }
+  Cx<T> xn = shdn(G, 1, P);
+  if (p == P - 1) xn = cz<T>();
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    Cx<T> t = mul(de[i], xn);
+    d[i] = Cx<T>{ga[i].x + t.x, ga[i].y + t.y};
+  }
+}
+
 }  // namespace tri
 }  // namespace pd
