@@ -39,7 +39,7 @@ STAGE_BOUND = {"fft_fwd": "hbm", "fft_inv": "hbm", "line_solve": "hbm", "matvec"
                "dot": "hbm", "update": "hbm", "other": "hbm", "xform_fwd": "mfma",
                "xform_inv": "mfma"}
 
-STAGE_KERNEL = {"fft_fwd": "k_fft_fwd", "fft_inv": "k_fft_inv", "line_solve": "k_line_solve",
+STAGE_KERNEL = {"fft_fwd": "k_fft_fwd", "fft_inv": "k_fft_inv", "line_solve": "k_schur_sweep",
                 "matvec": "k_matvec", "dot": "k_mdot", "update": "k_update", "other": "k_reduce",
                 "xform_fwd": "k_gemm", "xform_inv": "k_gemm"}
 
@@ -55,8 +55,24 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+                    help="profile summary holding a 'traffic: {...}' line with the measured HBM "
+                         "bytes per launch of the dominant kernel (default: profiles/<kernel>_<workload>_traffic.md)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized float64 tensor 3 times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int) -> None:
+    """A plain device-to-device copy of known size, for calibrating HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}), flush=True)
 
 
 def make_inputs(cfg, torch, pd):
@@ -107,29 +123,57 @@ def run_precision(cfg, prec, args, torch):
     return out, pd, u_keep
 
 
+KERNEL_SOURCES = {"k_schur_sweep": ("kernels_sweep.hip", "tri_device.h")}
+
+
+def measured_traffic(path, kernel, workload, prec):
+    """HBM bytes per launch from a committed counter summary, or None.
+
+    The summary's 'traffic:' line names the kernel, workload and precision it was
+    measured on and the sha256 of the kernel's sources; any mismatch (the kernel
+    changed since the counters were read) gives None.
+    """
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = path or os.path.join(here, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic: "):
+                rec = json.loads(line[len("traffic: "):])
+    if not rec or (rec.get("kernel"), rec.get("workload"), rec.get("prec")) != (kernel, workload, prec):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(here, "paper_2005_09158_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def roofline(run, cfg, traffic_file):
     stages = run["stages"]
     name = max(stages, key=lambda k: stages[k][0])
     ms, cnt, by, fl = stages[name]
     bound = STAGE_BOUND[name]
     if name == "line_solve" and cfg.dim == 2 and cfg.ax != 0.0:
-        bound = "alu"   # Schur back-sweep: coupling products on the vector ALUs
+        bound = "mfma"  # Schur back-sweep: the coupling product runs on MFMA
     avg_s = ms / 1e3 / max(cnt, 1)
     if bound == "hbm":
         achieved = by / max(cnt, 1) / avg_s / 1e9
         peak, unit = PEAK["hbm_GBs"], "GB/s"
     elif bound == "mfma":
         achieved = fl / max(cnt, 1) / avg_s / 1e12
-        peak, unit = PEAK["mfma_TFs"][run["prec"]], "TFLOP/s"
+        # the back-sweep's products run in the line precision (float32 in mixed modes)
+        key = run["prec"] if name != "line_solve" else ("fp64" if run["prec"] == "fp64" else "fp32")
+        peak, unit = PEAK["mfma_TFs"][key], "TFLOP/s"
     else:
         achieved = fl / max(cnt, 1) / avg_s / 1e12
         peak, unit = PEAK["vector_TFs"][run["prec"]], "TFLOP/s"
-    traffic = None
-    if traffic_file and os.path.exists(traffic_file):
-        with open(traffic_file) as fh:
-            t = json.load(fh)
-        if t.get("kernel") == STAGE_KERNEL.get(name):
-            traffic = t.get("bytes_per_launch")
+    traffic = measured_traffic(traffic_file, STAGE_KERNEL[name], cfg.name, run["prec"])
     return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": STAGE_KERNEL[name],
             "stage": name, "launches": cnt, "avg_launch_ms": round(ms / max(cnt, 1), 5),
@@ -170,6 +214,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
               f"single-GPU in this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
