@@ -43,7 +43,7 @@ constexpr int NT = 256;
 // In-place forward Stockham FFT of `ncol` columns of length Nt (column stride
 // ld) in LDS.  EPT = complex values held per thread in a pass (>= ncol*Nt/NT).
 template <typename T, int EPT>
-__device__ void fft_columns(typename V2<T>::t* sm, int ncol, int ld, int Nt, int logNt,
+__device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int ld, int Nt, int logNt,
                             const typename V2<T>::t* __restrict__ tw) {
   using C = typename V2<T>::t;
   int Ns = 1;
@@ -120,138 +120,228 @@ __device__ void fft_columns(typename V2<T>::t* sm, int ncol, int ld, int Nt, int
   }
 }
 
-template <typename T, int EPT>
-__global__ __launch_bounds__(NT) void k_fft_fwd(const double* __restrict__ x, T* __restrict__ spec,
-                                                const double* __restrict__ gam,
-                                                const double* __restrict__ bscale,
-                                                const typename V2<T>::t* __restrict__ tw, int Nt,
-                                                int logNt, int S, int sx, int sy, int logTX,
-                                                int reverse) {
+// Tile width TX (spatial unknowns per workgroup) and the per-thread register
+// budget of one FFT pass; see choose_shape.
+template <typename T> struct FftTraits;
+template <> struct FftTraits<float> { static constexpr int EPT = 32; };
+template <> struct FftTraits<double> { static constexpr int EPT = 16; };
+
+// Loads in flight per thread while the time columns are staged into LDS.
+constexpr int LOAD_BATCH = 16;
+
+// Copies the Nt-entry twiddle table into LDS behind the data columns.
+template <typename C>
+__device__ __forceinline__ void stage_twiddles(C* smtw, const C* __restrict__ tw, int Nt) {
+  for (int i = threadIdx.x; i < Nt; i += NT) smtw[i] = tw[i];
+}
+
+// Reads the pair of real time samples (s, s+1) at one time row; columns past
+// the spatial extent read as zero.  `vec` is set when the row start is
+// 16-byte aligned for every row (S even), which allows one double2 load.
+__device__ __forceinline__ double2 load_pair(const double* __restrict__ row, int s, int S, bool vec) {
+  if (vec && s + 1 < S) return *reinterpret_cast<const double2*>(row + s);
+  double2 v{0.0, 0.0};
+  if (s < S) v.x = row[s];
+  if (s + 1 < S) v.y = row[s + 1];
+  return v;
+}
+
+template <typename T, int TX>
+__global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x, T* __restrict__ spec,
+                                                   const double* __restrict__ gam,
+                                                   const double* __restrict__ bscale,
+                                                   const typename V2<T>::t* __restrict__ tw, int Nt,
+                                                   int logNt, int S, int sx, int sy, int reverse) {
   using C = typename V2<T>::t;
+  constexpr int EPT = FftTraits<T>::EPT;
+  constexpr int NCOL = TX / 2;           // complex columns: one per pair of real columns
+  constexpr int RPI = NT / NCOL;         // time rows per load sweep
   extern __shared__ __align__(16) unsigned char smraw[];
   C* sm = reinterpret_cast<C*>(smraw);
-  T* smT = reinterpret_cast<T*>(smraw);
-  const int TX = 1 << logTX, ld = Nt + 1, F = (Nt >> 1) + 1;
+  const int ld = Nt + 1, F = (Nt >> 1) + 1;
+  C* smtw = sm + NCOL * ld;
   const int b = blockIdx.y;
   const int s0 = blockIdx.x * TX;
   const double* xb = x + (int64_t)b * Nt * S;
   const double sc = bscale ? bscale[b] : 1.0;
-  for (int e = threadIdx.x; e < (Nt << logTX); e += NT) {
-    int n = e >> logTX, c = e & (TX - 1);
-    int s = s0 + c;
-    int nsrc = reverse ? (Nt - 1 - n) : n;
-    double v = 0.0;
-    if (s < S) v = xb[(int64_t)nsrc * S + s] * (gam[n] * sc);
-    smT[2 * ((c >> 1) * ld + n) + (c & 1)] = (T)v;
+  const bool vec = (S & 1) == 0;
+  stage_twiddles(smtw, tw, Nt);
+  // 1. stage: lane j of a row reads real columns (2j, 2j+1) with one 16-byte
+  //    load and stores them as the complex value r_2j + i r_2j+1 of column j.
+  {
+    const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
+    const int s = s0 + 2 * j;
+    for (int n0 = 0; n0 < Nt; n0 += RPI * LOAD_BATCH) {
+      double2 v[LOAD_BATCH];
+#pragma unroll
+      for (int u = 0; u < LOAD_BATCH; ++u) {
+        const int n = n0 + r + u * RPI;
+        if (n < Nt) {
+          const int nsrc = reverse ? (Nt - 1 - n) : n;
+          v[u] = load_pair(xb + (int64_t)nsrc * S, s, S, vec);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LOAD_BATCH; ++u) {
+        const int n = n0 + r + u * RPI;
+        if (n < Nt) {
+          const double g = gam[n] * sc;
+          sm[j * ld + n] = C{(T)(v[u].x * g), (T)(v[u].y * g)};
+        }
+      }
+    }
   }
   __syncthreads();
-  fft_columns<T, EPT>(sm, TX >> 1, ld, Nt, logNt, tw);
+  fft_columns<T, EPT>(sm, NCOL, ld, Nt, logNt, smtw);
+  // 2. Hermitian split of column j into the half spectra of real columns 2j
+  //    and 2j+1, written as (re, re) and (im, im) pairs of adjacent x.
   T* specb = spec + (int64_t)b * F * sy * 2 * sx;
-  for (int e = threadIdx.x; e < (F << logTX); e += NT) {
-    int k = e >> logTX, c = e & (TX - 1);
-    int s = s0 + c;
-    if (s >= S) continue;
-    const C* col = sm + (c >> 1) * ld;
+  const bool vout = (sx & 1) == 0;
+  const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
+  const int s = s0 + 2 * j;
+  if (s >= S) return;
+  const int y = s / sx, xx = s - y * sx;
+  const int y1 = (s + 1) / sx, xx1 = (s + 1) - y1 * sx;
+  for (int k = r; k < F; k += RPI) {
+    const C* col = sm + j * ld;
     C zk = col[k], zm = col[(Nt - k) & (Nt - 1)];
-    T re, im;
-    if ((c & 1) == 0) {
-      re = (T)0.5 * (zk.x + zm.x);
-      im = (T)0.5 * (zk.y - zm.y);
-    } else {
-      re = (T)0.5 * (zk.y + zm.y);
-      im = (T)0.5 * (zm.x - zk.x);
-    }
-    int y = s / sx, xx = s - y * sx;
+    const T ar = (T)0.5 * (zk.x + zm.x), ai = (T)0.5 * (zk.y - zm.y);
+    const T br = (T)0.5 * (zk.y + zm.y), bi = (T)0.5 * (zm.x - zk.x);
     T* dst = specb + ((int64_t)k * sy + y) * 2 * sx + xx;
-    dst[0] = re;
-    dst[sx] = im;
+    if (vout && s + 1 < S) {
+      *reinterpret_cast<C*>(dst) = C{ar, br};
+      *reinterpret_cast<C*>(dst + sx) = C{ai, bi};
+    } else {
+      dst[0] = ar;
+      dst[sx] = ai;
+      if (s + 1 < S) {
+        T* d1 = specb + ((int64_t)k * sy + y1) * 2 * sx + xx1;
+        d1[0] = br;
+        d1[sx] = bi;
+      }
+    }
   }
 }
 
-template <typename T, int EPT, typename Tout>
-__global__ __launch_bounds__(NT) void k_fft_inv(const T* __restrict__ spec, Tout* __restrict__ z,
-                                                const double* __restrict__ invgam,
-                                                const typename V2<T>::t* __restrict__ tw, int Nt,
-                                                int logNt, int S, int sx, int sy, int logTX,
-                                                int accumulate, int reverse) {
+template <typename Tout> struct Out2;
+template <> struct Out2<float> { using t = float2; };
+template <> struct Out2<double> { using t = double2; };
+
+template <typename T, int TX, typename Tout>
+__global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, Tout* __restrict__ z,
+                                                   const double* __restrict__ invgam,
+                                                   const typename V2<T>::t* __restrict__ tw, int Nt,
+                                                   int logNt, int S, int sx, int sy, int accumulate,
+                                                   int reverse) {
   using C = typename V2<T>::t;
+  using O2 = typename Out2<Tout>::t;
+  constexpr int EPT = FftTraits<T>::EPT;
+  constexpr int NCOL = TX / 2;
+  constexpr int RPI = NT / NCOL;
   extern __shared__ __align__(16) unsigned char smraw[];
   C* sm = reinterpret_cast<C*>(smraw);
-  T* smT = reinterpret_cast<T*>(smraw);
-  const int TX = 1 << logTX, ld = Nt + 1, F = (Nt >> 1) + 1, half = Nt >> 1;
+  const int ld = Nt + 1, F = (Nt >> 1) + 1, half = Nt >> 1;
+  C* smtw = sm + NCOL * ld;
   const int b = blockIdx.y;
   const int s0 = blockIdx.x * TX;
   const T* specb = spec + (int64_t)b * F * sy * 2 * sx;
-  // 1. load half spectra: X_a[k] -> slot k, X_b[k] -> slot Nt-k; DC and
-  //    Nyquist keep only their real parts (they are real for real data).
-  for (int e = threadIdx.x; e < (F << logTX); e += NT) {
-    int k = e >> logTX, c = e & (TX - 1);
-    int s = s0 + c;
-    T re = 0, im = 0;
-    if (s < S) {
-      int y = s / sx, xx = s - y * sx;
-      const T* src = specb + ((int64_t)k * sy + y) * 2 * sx + xx;
-      re = src[0];
-      im = src[sx];
-    }
-    int cc = c >> 1;
-    if (k == 0 || k == half) {
-      smT[2 * (cc * ld + k) + (c & 1)] = re;
-    } else if ((c & 1) == 0) {
-      sm[cc * ld + k] = C{re, im};
-    } else {
-      sm[cc * ld + Nt - k] = C{re, im};
+  stage_twiddles(smtw, tw, Nt);
+  const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
+  const int s = s0 + 2 * j;
+  const bool vin = (sx & 1) == 0;
+  // 1. merge the half spectra X_a (column 2j) and X_b (column 2j+1) into the
+  //    full circle of Z = X_a + i X_b, stored conjugated for the forward
+  //    kernel: ifft(Z) = conj(fft(conj Z)) / Nt.  DC and Nyquist keep only
+  //    the real parts (real data).
+  {
+    const int y = s / sx, xx = s - y * sx;
+    const int y1 = (s + 1) / sx, xx1 = (s + 1) - y1 * sx;
+    C* col = sm + j * ld;
+    for (int k0 = 0; k0 < F; k0 += RPI * LOAD_BATCH) {
+      C a[LOAD_BATCH], bb[LOAD_BATCH];
+#pragma unroll
+      for (int u = 0; u < LOAD_BATCH; ++u) {
+        const int k = k0 + r + u * RPI;
+        a[u] = C{0, 0};
+        bb[u] = C{0, 0};
+        if (k < F && s < S) {
+          const T* src = specb + ((int64_t)k * sy + y) * 2 * sx + xx;
+          if (vin && s + 1 < S) {
+            C re = *reinterpret_cast<const C*>(src), im = *reinterpret_cast<const C*>(src + sx);
+            a[u] = C{re.x, im.x};
+            bb[u] = C{re.y, im.y};
+          } else {
+            a[u] = C{src[0], src[sx]};
+            if (s + 1 < S) {
+              const T* s1 = specb + ((int64_t)k * sy + y1) * 2 * sx + xx1;
+              bb[u] = C{s1[0], s1[sx]};
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LOAD_BATCH; ++u) {
+        const int k = k0 + r + u * RPI;
+        if (k < F) {
+          const C A = a[u], Bv = bb[u];
+          if (k == 0 || k == half) {
+            col[k] = C{A.x, -Bv.x};
+          } else {
+            col[k] = C{A.x - Bv.y, -(A.y + Bv.x)};
+            col[Nt - k] = C{A.x + Bv.y, A.y - Bv.x};
+          }
+        }
+      }
     }
   }
   __syncthreads();
-  // 2. Z = X_a + i X_b on the full circle, stored conjugated
-  const int ncol = TX >> 1;
-  for (int e = threadIdx.x; e < (ncol << (logNt - 1)); e += NT) {
-    int cc = e >> (logNt - 1), k = e & (half - 1);
-    C* col = sm + cc * ld;
-    if (k == 0) {
-      C z0 = col[0], zh = col[half];
-      col[0] = C{z0.x, -z0.y};
-      col[half] = C{zh.x, -zh.y};
-    } else {
-      C A = col[k], Bv = col[Nt - k];
-      col[k] = C{A.x - Bv.y, -(A.y + Bv.x)};
-      col[Nt - k] = C{A.x + Bv.y, -(Bv.x - A.y)};
-    }
-  }
-  __syncthreads();
-  fft_columns<T, EPT>(sm, ncol, ld, Nt, logNt, tw);
-  // 3. z = conj(fft(conj Z)) / Nt, split into the two real columns, Gamma^{-1}
+  fft_columns<T, EPT>(sm, NCOL, ld, Nt, logNt, smtw);
+  // 2. z = conj(fft(conj Z)) / Nt: real column 2j is Re, column 2j+1 is -Im;
+  //    Gamma^{-1} (with the 1/Nt) in float64.
+  if (s >= S) return;
   Tout* zb = z + (int64_t)b * Nt * S;
-  for (int e = threadIdx.x; e < (Nt << logTX); e += NT) {
-    int n = e >> logTX, c = e & (TX - 1);
-    int s = s0 + c;
-    if (s >= S) continue;
-    C yv = sm[(c >> 1) * ld + n];
-    double v = ((c & 1) ? -(double)yv.y : (double)yv.x) * invgam[n];
-    int nd = reverse ? (Nt - 1 - n) : n;
+  const bool vec = (S & 1) == 0 && s + 1 < S;
+  for (int n = r; n < Nt; n += RPI) {
+    const C yv = sm[j * ld + n];
+    const double ig = invgam[n];
+    const double v0 = (double)yv.x * ig, v1 = -(double)yv.y * ig;
+    const int nd = reverse ? (Nt - 1 - n) : n;
     Tout* dst = zb + (int64_t)nd * S + s;
-    if (accumulate) *dst = (Tout)((double)*dst + v);
-    else *dst = (Tout)v;
+    if (vec) {
+      O2* d2 = reinterpret_cast<O2*>(dst);
+      if (accumulate) {
+        const O2 o = *d2;
+        *d2 = O2{(Tout)((double)o.x + v0), (Tout)((double)o.y + v1)};
+      } else {
+        *d2 = O2{(Tout)v0, (Tout)v1};
+      }
+    } else {
+      if (accumulate) dst[0] = (Tout)((double)dst[0] + v0);
+      else dst[0] = (Tout)v0;
+      if (s + 1 < S) {
+        if (accumulate) dst[1] = (Tout)((double)dst[1] + v1);
+        else dst[1] = (Tout)v1;
+      }
+    }
   }
 }
 
-struct FftShape { int logTX; int ept; size_t lds; };
+struct FftShape { int TX; size_t lds; };
 
+// Widest tile (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex
+// columns of Nt+1 entries plus the twiddle table -- lets two workgroups share
+// a CU, and whose FFT pass fits the per-thread register budget.
 FftShape choose_shape(const Plan& pl) {
   const Geom& g = pl.g;
-  const size_t csize = (pl.prec == Prec::F64) ? 16 : 8;
-  const size_t budget = 66 * 1024;
-  int logTX = 4;  // TX = 16
-  while (logTX > 1 && (size_t)((1 << logTX) / 2) * (g.nt + 1) * csize > budget) --logTX;
-  // do not tile wider than the spatial extent needs
-  while (logTX > 1 && (1 << (logTX - 1)) >= g.S) --logTX;
-  int ncol = (1 << logTX) / 2;
-  int need = (ncol * g.nt + NT - 1) / NT;
-  int ept = 4;
-  while (ept < need) ept <<= 1;
-  FftShape sh{logTX, ept, (size_t)ncol * (g.nt + 1) * csize};
-  return sh;
+  const bool f64 = pl.prec == Prec::F64;
+  const size_t csize = f64 ? 16 : 8;
+  const int ept = f64 ? FftTraits<double>::EPT : FftTraits<float>::EPT;
+  const size_t budget = 79 * 1024;
+  int TX = 32;
+  auto lds = [&](int tx) { return (size_t)(tx / 2) * (g.nt + 1) * csize + (size_t)g.nt * csize; };
+  while (TX > 2 && (lds(TX) > budget || (int64_t)(TX / 2) * g.nt > (int64_t)ept * NT)) TX >>= 1;
+  while (TX > 2 && TX / 2 >= g.S) TX >>= 1;  // no wider than the spatial extent needs
+  return FftShape{TX, lds(TX)};
 }
 
 template <typename T>
@@ -261,16 +351,16 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
   FftShape sh = choose_shape(pl);
   int logNt = 0;
   while ((1 << logNt) < g.nt) ++logNt;
-  dim3 grid((g.S + (1 << sh.logTX) - 1) >> sh.logTX, g.B);
-#define PD_FWD(E)                                                                          \
-  case E:                                                                                  \
-    hipFuncSetAttribute((const void*)k_fft_fwd<T, E>,                                      \
+  dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
+#define PD_FWD(W)                                                                          \
+  case W:                                                                                  \
+    hipFuncSetAttribute((const void*)k_fft_fwd<T, W>,                                      \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
-    k_fft_fwd<T, E><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt, logNt,   \
-                                             (int)g.S, g.sx, g.sy, sh.logTX, reverse);     \
+    k_fft_fwd<T, W><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt, logNt,   \
+                                             (int)g.S, g.sx, g.sy, reverse);               \
     break;
-  switch (sh.ept) {
-    PD_FWD(4) PD_FWD(8) PD_FWD(16) PD_FWD(32)
+  switch (sh.TX) {
+    PD_FWD(2) PD_FWD(4) PD_FWD(8) PD_FWD(16) PD_FWD(32)
     default: break;
   }
 #undef PD_FWD
@@ -283,17 +373,17 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
   FftShape sh = choose_shape(pl);
   int logNt = 0;
   while ((1 << logNt) < g.nt) ++logNt;
-  dim3 grid((g.S + (1 << sh.logTX) - 1) >> sh.logTX, g.B);
-#define PD_INV(E)                                                                          \
-  case E:                                                                                  \
-    hipFuncSetAttribute((const void*)k_fft_inv<T, E, Tout>,                                \
+  dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
+#define PD_INV(W)                                                                          \
+  case W:                                                                                  \
+    hipFuncSetAttribute((const void*)k_fft_inv<T, W, Tout>,                                \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
-    k_fft_inv<T, E, Tout><<<grid, NT, sh.lds, s>>>(spec, z, pl.d_invgam, tw, g.nt, logNt,  \
-                                                   (int)g.S, g.sx, g.sy, sh.logTX,         \
-                                                   accumulate, reverse);                   \
+    k_fft_inv<T, W, Tout><<<grid, NT, sh.lds, s>>>(spec, z, pl.d_invgam, tw, g.nt, logNt,  \
+                                                   (int)g.S, g.sx, g.sy, accumulate,       \
+                                                   reverse);                               \
     break;
-  switch (sh.ept) {
-    PD_INV(4) PD_INV(8) PD_INV(16) PD_INV(32)
+  switch (sh.TX) {
+    PD_INV(2) PD_INV(4) PD_INV(8) PD_INV(16) PD_INV(32)
     default: break;
   }
 #undef PD_INV
