@@ -72,7 +72,7 @@ typedef enum {
   PD_PREC_FP64 = 0,           /* FFT, x-transform and line solves in float64 */
   PD_PREC_FP32 = 1,           /* FFT, x-transform and line solves in float32 */
   PD_PREC_FP32_BF16GEMM = 2,  /* as FP32; x-transform on bf16 MFMA with fp32 accumulation,
-                                 operands split into bf16 hi + lo parts (three products:
+                                 operands split into three bf16 parts (six products:
                                  float32-level accuracy at bf16 instruction rate) */
   PD_PREC_FP32_BF16X1 = 3     /* as FP32; x-transform as one bf16 product (fastest, least
                                  accurate: the preconditioner error grows with the

@@ -24,9 +24,9 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 size_t compute_elem_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
 // bytes of one x-transform matrix of `elems` entries in the compute format
-// (split bf16 keeps hi and lo parts plus a float32 copy for ragged sizes)
+// (split bf16 keeps hi, mid and lo parts plus a float32 copy for ragged sizes)
 size_t gemm_matrix_bytes(Prec p, size_t elems) {
-  return p == Prec::BF16 ? elems * (2 + 2 + 4) : elems * compute_elem_bytes(p);
+  return p == Prec::BF16 ? elems * (2 + 2 + 2 + 4) : elems * compute_elem_bytes(p);
 }
 }  // namespace
 
@@ -758,18 +758,23 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
         else if (pl->prec == Prec::F32) store_compute<float>(dst, src, s, keep);
         else if (pl->prec == Prec::BF16X1) store_compute<Bf16Bits>(dst, src, s, keep);
         else {
-          // hi part, lo part (residual of the hi rounding), float32 copy
-          std::vector<double> hi(src.size()), lo(src.size());
+          // three bf16 parts of the float32 value (hi, then the rounded
+          // residuals mid and lo; the float32 subtractions are exact), then
+          // a float32 copy
+          std::vector<double> part[3];
+          for (auto& v : part) v.resize(src.size());
           for (size_t i = 0; i < src.size(); ++i) {
-            uint32_t u = (uint32_t)to_bf16_bits(src[i]) << 16;
-            float h;
-            std::memcpy(&h, &u, 4);
-            hi[i] = h;
-            lo[i] = (double)((float)src[i] - h);
+            float rest = (float)src[i];
+            for (int a = 0; a < 3; ++a) {
+              uint32_t u = (uint32_t)to_bf16_bits(rest) << 16;
+              float h;
+              std::memcpy(&h, &u, 4);
+              part[a][i] = h;
+              rest -= h;
+            }
           }
-          store_compute<Bf16Bits>(dst, hi, s, keep);
-          store_compute<Bf16Bits>((char*)dst + 2 * src.size(), lo, s, keep);
-          store_compute<float>((char*)dst + 4 * src.size(), src, s, keep);
+          for (int a = 0; a < 3; ++a) store_compute<Bf16Bits>((char*)dst + 2 * a * src.size(), part[a], s, keep);
+          store_compute<float>((char*)dst + 6 * src.size(), src, s, keep);
         }
       }
       if (pl->schur) {

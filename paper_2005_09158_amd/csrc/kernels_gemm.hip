@@ -21,6 +21,10 @@
 //   float32  v_mfma_f32_16x16x4f32   (64 x 64 x 16 tiles)
 //   bf16     v_mfma_f32_16x16x32_bf16 with float32 accumulation (128 x 128 x 32 tiles);
 //            float32 rows are rounded to bf16 (nearest even) on the way into LDS.
+//            Split mode writes each operand as hi + mid + lo in bf16 (24
+//            significand bits, exact residuals) and keeps the six partial
+//            products down to relative size 2^-16, so the result carries
+//            float32-level accuracy at the bf16 instruction rate.
 // Fragment layout (16x16xK MFMA): lane l supplies A[l % 16][k-slice l / 16]
 // and B[k-slice l / 16][l % 16]; accumulator v of lane l is C[4 (l / 16) + v][l % 16]
 // for the float32 and bf16 instructions and C[l / 16 + 4 v][l % 16] for the
@@ -174,11 +178,13 @@ void launch_gemm(const Ts* A, const Tc* Bt, Ts* C, int64_t M, int N, int K, hipS
 
 // bf16 MFMA path for float32 rows (K % 32 == 0): float4 row loads, the rows
 // rounded to bf16 on the way into LDS, 16-byte fragment reads, the next k-tile
-// prefetched into registers while the current one is multiplied.  SPLIT = 3
-// keeps float32-level accuracy with bf16 instructions: a = a_hi + a_lo and
-// b = b_hi + b_lo (each bf16), a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, the
-// dropped a_lo b_lo term being 2^-16 relative.  SPLIT = 1 is the plain
-// single bf16 product.  Bt holds b_hi ([N][K]) followed by b_lo.
+// prefetched into registers while the current one is multiplied.  SPLIT = 6
+// keeps float32-level accuracy with bf16 instructions: a = a0 + a1 + a2 and
+// b = b0 + b1 + b2 (bf16 parts of relative size 1, 2^-8, 2^-16), and
+// a b ~ sum of a_x b_y over x + y <= 2, the dropped terms being 2^-24 relative
+// or less.  SPLIT = 3 is the two-part form (hi + lo, about 16 significand
+// bits), SPLIT = 1 the plain single bf16 product.  Bt holds the parts
+// ([N][K] each) one after the other.
 // Tiles: 128 x 128 x 32, 2 x 2 waves of 64 x 64 (4 x 4 blocks of 16 x 16).
 // Blocks are ordered so that the N-tiles sharing one row block of A run on
 // the same XCD (consecutive workgroup ids are dealt round-robin to the 8
@@ -199,7 +205,8 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
                                                   float* __restrict__ C, int64_t M, int N, int K,
                                                   int ntn, int64_t nblocks) {
   constexpr int BM = 128, BN = 128, BK = 32, LD = BK + 8;   // LDS row: 80 bytes
-  constexpr int NA = (SPLIT == 3) ? 2 : 1;
+  // operand terms: 1 (plain bf16), 2 (hi + lo), 3 (hi + mid + lo)
+  constexpr int NA = (SPLIT == 6) ? 3 : (SPLIT == 3) ? 2 : 1;
   __shared__ __align__(16) unsigned short As[NA][BM * LD];
   __shared__ __align__(16) unsigned short Bs[NA][BN * LD];
 
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
-  const unsigned short* Blo = Bt + (int64_t)N * K;
+  const int64_t NKp = (int64_t)N * K;   // elements per bf16 part of the matrix
 
   // per-thread staging: A 4 x float4 (rows tid/8 + 32 i, k = 4 (tid%8)),
   // B 2 x 16 bytes per part (rows tid/4 + 64 i, k = 8 (tid%4))
@@ -229,8 +236,9 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
     for (int i = 0; i < 2; ++i) {
       int gn = n0 + (tid >> 2) + 64 * i;
       int64_t off = (int64_t)gn * K + k0 + 8 * (tid & 3);
-      rb[0][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Bt + off) : uint4{0, 0, 0, 0};
-      if constexpr (NA == 2) rb[1][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Blo + off) : uint4{0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        rb[a][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Bt + a * NKp + off) : uint4{0, 0, 0, 0};
     }
   };
   auto sstore = [&]() {
@@ -238,14 +246,20 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
     for (int i = 0; i < 4; ++i) {
       int r = (tid >> 3) + 32 * i, c = 4 * (tid & 7);
       float v[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
-      us4 hi, lo;
+      // exact residuals in float32: v - hi and (v - hi) - mid have at most 16
+      // and 8 significant bits beyond the parts already taken
+      us4 part[NA];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        hi[q] = bf16_bits(v[q]);
-        if constexpr (NA == 2) lo[q] = bf16_bits(v[q] - bf16_val(hi[q]));
+        float rest = v[q];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          part[a][q] = bf16_bits(rest);
+          if (a + 1 < NA) rest -= bf16_val(part[a][q]);
+        }
       }
-      *reinterpret_cast<us4*>(&As[0][r * LD + c]) = hi;
-      if constexpr (NA == 2) *reinterpret_cast<us4*>(&As[1][r * LD + c]) = lo;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<us4*>(&As[a][r * LD + c]) = part[a];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -281,11 +295,18 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        if constexpr (NA == 2) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+        // terms of size 2^-16 and above (relative): a_x b_y with x + y < NA,
+        // the smallest first
+        if constexpr (NA == 3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
         }
+        if constexpr (NA >= 2) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
       }
   }
 #pragma unroll
@@ -335,12 +356,12 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
     case Prec::BF16X1: {
       const bool split = pl.prec == Prec::BF16;
       if (K % 32 == 0) {
-        if (split) launch_gemm_bf16<3>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s);
+        if (split) launch_gemm_bf16<6>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s);
         else launch_gemm_bf16<1>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s);
       } else if (split) {
         // ragged K (nx not a multiple of 16): the float32 MFMA kernel on the float32
-        // copy of the matrix that follows the two bf16 parts
-        const float* B32 = (const float*)((const unsigned short*)Bt + (size_t)2 * N * K);
+        // copy of the matrix that follows the three bf16 parts
+        const float* B32 = (const float*)((const unsigned short*)Bt + (size_t)3 * N * K);
         launch_gemm<float, float, 64, 64, 16>((const float*)in, B32, (float*)out, M, N, K, s);
       } else {
         launch_gemm<float, __bf16, 128, 128, 32>((const float*)in, (const __bf16*)Bt, (float*)out, M, N, K, s);

@@ -62,7 +62,18 @@ template <> struct V4<double> { using t = double4; };
 // four-vector to MFMA step s: the k order inside the block is permuted, the
 // same way for A (W rows) and B (T rows), which leaves the sum unchanged.
 // Each wave covers its own RB x 16 rows; T rows are shared through the cache.
-template <typename T, int NB, int RB>
+template <typename T> __device__ __forceinline__ typename V4<T>::t load4(const T* ptr, int j, int sx, bool vec) {
+  using Q4 = typename V4<T>::t;
+  if (vec) return *reinterpret_cast<const Q4*>(ptr + j);
+  Q4 v{};
+  v.x = ptr[j];
+  if (j + 1 < sx) v.y = ptr[j + 1];
+  if (j + 2 < sx) v.z = ptr[j + 2];
+  if (j + 3 < sx) v.w = ptr[j + 3];
+  return v;
+}
+
+template <typename T, int NB, int RB, bool VEC = true>
 __device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, const T* tim, int sx,
                                                 int sy, int k0, int nk, int kend, int wave, int lr,
                                                 int lk, typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
@@ -80,8 +91,8 @@ __device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, co
     const bool jok = j < sx;
     Q4 tr{}, ti{};
     if (qok && jok) {
-      tr = *reinterpret_cast<const Q4*>(trow + j);
-      ti = *reinterpret_cast<const Q4*>(irow + j);
+      tr = load4(trow, j, sx, VEC);
+      ti = load4(irow, j, sx, VEC);
     }
     Q4 ar[RB], ai[RB];
 #pragma unroll
@@ -89,8 +100,8 @@ __device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, co
       const int r = r0 + 16 * i;
       if (jok && r < sy) {
         const T* row = slice + (int64_t)r * 2 * sx;
-        ar[i] = *reinterpret_cast<const Q4*>(row + j);
-        ai[i] = *reinterpret_cast<const Q4*>(row + sx + j);
+        ar[i] = load4(row, j, sx, VEC);
+        ai[i] = load4(row + sx, j, sx, VEC);
       } else {
         ar[i] = Q4{};
         ai[i] = Q4{};
@@ -120,8 +131,366 @@ __device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, co
   }
 }
 
+// Fragments of one 16-mode step of the coupling product: T rows of this
+// lane's output column and RB rows of solved lines (real, imaginary parts).
+template <typename T, int RB> struct CouplingFrag {
+  typename V4<T>::t tr, ti, ar[RB], ai[RB];
+};
+
+template <typename T, int RB, bool VEC>
+__device__ __forceinline__ void load_frag(CouplingFrag<T, RB>& f, const T* slice, const T* trow,
+                                          const T* irow, int sx, int sy, int j, bool qok, int r0) {
+  using Q4 = typename V4<T>::t;
+  const bool jok = j < sx;
+  f.tr = Q4{};
+  f.ti = Q4{};
+  if (qok && jok) {
+    f.tr = load4(trow, j, sx, VEC);
+    f.ti = load4(irow, j, sx, VEC);
+  }
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int r = r0 + 16 * i;
+    if (jok && r < sy) {
+      const T* row = slice + (int64_t)r * 2 * sx;
+      f.ar[i] = load4(row, j, sx, VEC);
+      f.ai[i] = load4(row + sx, j, sx, VEC);
+    } else {
+      f.ar[i] = Q4{};
+      f.ai[i] = Q4{};
+    }
+  }
+}
+
+template <typename T, int NB, int RB>
+__device__ __forceinline__ void mma_frag(const CouplingFrag<T, RB>& f, int part,
+                                         typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+  using MF = SweepMfma<T>;
+  constexpr int NCB = 2 * NB / 16;
+  const T trv[4] = {f.tr.x, f.tr.y, f.tr.z, f.tr.w}, tiv[4] = {f.ti.x, f.ti.y, f.ti.z, f.ti.w};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const T b_re_r = trv[st], b_re_i = -tiv[st], b_im_r = tiv[st], b_im_i = trv[st];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const T av_r = (st == 0) ? f.ar[i].x : (st == 1) ? f.ar[i].y : (st == 2) ? f.ar[i].z : f.ar[i].w;
+      const T av_i = (st == 0) ? f.ai[i].x : (st == 1) ? f.ai[i].y : (st == 2) ? f.ai[i].z : f.ai[i].w;
+      if constexpr (NCB == 2) {
+        acc[i][0] = MF::run(av_r, b_re_r, acc[i][0]);
+        acc[i][0] = MF::run(av_i, b_re_i, acc[i][0]);
+        acc[i][1] = MF::run(av_r, b_im_r, acc[i][1]);
+        acc[i][1] = MF::run(av_i, b_im_i, acc[i][1]);
+      } else {
+        acc[i][0] = MF::run(av_r, part ? b_im_r : b_re_r, acc[i][0]);
+        acc[i][0] = MF::run(av_i, part ? b_im_i : b_re_i, acc[i][0]);
+      }
+    }
+  }
+}
+
+// Coupling to the solved modes j >= kend with W read from global memory, the
+// fragments of the next 16 modes loaded while the current ones multiply.
+template <typename T, int NB, int RB, bool VEC>
+__device__ __forceinline__ void coupling_far(const T* slice, const T* tre, const T* tim, int sx, int sy,
+                                             int k0n, int kend, int cw, int lr, int lk,
+                                             typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+  constexpr int NCB = 2 * NB / 16;
+  const int q = (NCB == 2) ? lr : (lr & 7);
+  const int part = (NCB == 2) ? 0 : (lr >> 3);
+  const T* trow = tre + (int64_t)(k0n + q) * sx;
+  const T* irow = tim + (int64_t)(k0n + q) * sx;
+  const int r0 = cw * RB * 16 + lr;
+  if (kend >= sx) return;
+  CouplingFrag<T, RB> fa, fb;
+  load_frag<T, RB, VEC>(fa, slice, trow, irow, sx, sy, kend + 4 * lk, true, r0);
+#pragma unroll 1
+  for (int j0 = kend; j0 < sx; j0 += 32) {
+    const bool more = j0 + 16 < sx;
+    if (more) load_frag<T, RB, VEC>(fb, slice, trow, irow, sx, sy, j0 + 16 + 4 * lk, true, r0);
+    mma_frag<T, NB, RB>(fa, part, acc);
+    if (!more) break;
+    if (j0 + 32 < sx) load_frag<T, RB, VEC>(fa, slice, trow, irow, sx, sy, j0 + 32 + 4 * lk, true, r0);
+    mma_frag<T, NB, RB>(fb, part, acc);
+  }
+}
+
+// Coupling of the next block to the block just solved, with the solved lines
+// read from the LDS tile (lane group lk owns tile columns 4 lk .. 4 lk + 3,
+// the same permuted k order as coupling_direct).
+template <typename T, int NB, int RB, int R>
+__device__ __forceinline__ void coupling_lds(const T* sre, const T* sim, const T* tre, const T* tim,
+                                             int sx, int sy, int ldy, int k0n, int k0, int nk,
+                                             int cw, int lr, int lk,
+                                             typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+  using MF = SweepMfma<T>;
+  constexpr int NCB = 2 * NB / 16;
+  const int q = (NCB == 2) ? lr : (lr & 7);
+  const int part = (NCB == 2) ? 0 : (lr >> 3);
+  const int r0 = cw * RB * 16 + lr;
+#pragma unroll
+  for (int jb = 0; jb < NB; jb += 16) {
+    T trv[4], tiv[4];
+    T av_r[RB][4], av_i[RB][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int jj = jb + 4 * lk + st;
+      const bool ok = jj < nk;
+      trv[st] = ok ? tre[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
+      tiv[st] = ok ? tim[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int y = r0 + 16 * i;
+        const bool rok = ok && y < sy;
+        av_r[i][st] = rok ? sre[lidx(jj, y, ldy, R)] : (T)0;
+        av_i[i][st] = rok ? sim[lidx(jj, y, ldy, R)] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const T b_re_r = trv[st], b_re_i = -tiv[st], b_im_r = tiv[st], b_im_i = trv[st];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        if constexpr (NCB == 2) {
+          acc[i][0] = MF::run(av_r[i][st], b_re_r, acc[i][0]);
+          acc[i][0] = MF::run(av_i[i][st], b_re_i, acc[i][0]);
+          acc[i][1] = MF::run(av_r[i][st], b_im_r, acc[i][1]);
+          acc[i][1] = MF::run(av_i[i][st], b_im_i, acc[i][1]);
+        } else {
+          acc[i][0] = MF::run(av_r[i][st], part ? b_im_r : b_re_r, acc[i][0]);
+          acc[i][0] = MF::run(av_i[i][st], part ? b_im_i : b_re_i, acc[i][0]);
+        }
+      }
+    }
+  }
+}
+
+// 16-byte copies of a full tile (NB modes, sx % 4 == 0): each vector holds
+// MV consecutive modes of one row part; every thread issues all its loads
+// before its LDS stores.  MAXROWS bounds sy.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using t = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using t = double2; static constexpr int n = 2; };
+
+template <typename T> __device__ __forceinline__ T vget(const float4& v, int m) {
+  return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
+}
+template <typename T> __device__ __forceinline__ T vget(const double2& v, int m) {
+  return m == 0 ? v.x : v.y;
+}
+
+template <typename T, int NB, int MAXROWS>
+__device__ __forceinline__ void tile_load_vec(const T* slice, T* sre, T* sim, int k0, int sx, int sy,
+                                              int ldy, int R, int t, int nthr) {
+  using V = typename Vec16<T>::t;
+  constexpr int MV = Vec16<T>::n, NV = NB / MV;
+  constexpr int MAXE = MAXROWS * 2 * NV;
+  constexpr int MAXU = (MAXE + 191) / 192;   // nthr >= 192
+  const int total = sy * 2 * NV;
+  V v[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = t + u * nthr;
+    if (e < total) {
+      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+      v[u] = *reinterpret_cast<const V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = t + u * nthr;
+    if (e < total) {
+      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+      T* dst = comp ? sim : sre;
+#pragma unroll
+      for (int m = 0; m < MV; ++m) dst[lidx(kv * MV + m, y, ldy, R)] = vget<T>(v[u], m);
+    }
+  }
+}
+
+template <typename T, int NB, int MAXROWS>
+__device__ __forceinline__ void tile_store_vec(T* slice, const T* sre, const T* sim, int k0, int sx,
+                                               int sy, int ldy, int R, int t, int nthr) {
+  using V = typename Vec16<T>::t;
+  constexpr int MV = Vec16<T>::n, NV = NB / MV;
+  const int total = sy * 2 * NV;
+  for (int e = t; e < total; e += nthr) {
+    const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+    const T* src = comp ? sim : sre;
+    V v;
+    T* vv = reinterpret_cast<T*>(&v);
+#pragma unroll
+    for (int m = 0; m < MV; ++m) vv[m] = src[lidx(kv * MV + m, y, ldy, R)];
+    *reinterpret_cast<V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV) = v;
+  }
+}
+
+// Pipelined back-sweep: one workgroup of 1 + NCW waves per (right-hand side,
+// frequency) slice.  While wave 0 solves block b of NB modes (lines held in
+// registers, right-looking updates inside the block, DPP scans), waves 1..NCW
+// stage the tile of block b-1 and compute its coupling to every mode solved
+// before b on MFMA (RB 16-row blocks each); after the barrier they add the
+// coupling to block b itself from the LDS tile and subtract lambda2 times the
+// total.  Tiles and the in-block coupling coefficients lambda2 T are
+// double-buffered in LDS.  One wave per SIMD, so each wave has the whole
+// register file (wave 0 keeps NB x R complex values per lane).
+constexpr int NCW = 3;
+constexpr int SWT = 64 * (NCW + 1);
+
+template <typename T, int R, int P, int NB, int RB, bool VEC>
+__global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
+                                                     const T* __restrict__ tup, const T* __restrict__ lu,
+                                                     double lo, double up, int F, int sx, int sy, int ldy) {
+  static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
+  using MF = SweepMfma<T>;
+  constexpr int NCB = 2 * NB / 16;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  T* tiles = reinterpret_cast<T*>(smraw);       // [2 buffers][re, im][NB][ldy]
+  const int TS = 2 * NB * ldy;
+  T* tbs = tiles + 2 * TS;                      // [2 buffers][re, im][NB][NB]: lambda2 T_{q' q}, q' < q
+
+  const int n = blockIdx.x, b = blockIdx.y;
+  T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
+  const T* tre = tup;
+  const T* tim = tup + (int64_t)sx * sx;
+  const double2 l2 = lam[F + n];
+  const T l2r = (T)l2.x, l2i = (T)l2.y;
+  const int wave = threadIdx.x >> 6;
+  const int nblk = (sx + NB - 1) / NB;
+
+  auto stage_tb = [&](int buf, int k0, int nk, int t, int nthr) {
+    T* bt = tbs + buf * 2 * NB * NB;   // (re, im) pairs
+    for (int e = t; e < NB * NB; e += nthr) {
+      const int qa = e / NB, qb = e - qa * NB;
+      T tr = 0, ti = 0;
+      if (qa < qb && qb < nk) {
+        tr = tre[(int64_t)(k0 + qa) * sx + k0 + qb];
+        ti = tim[(int64_t)(k0 + qa) * sx + k0 + qb];
+      }
+      bt[2 * e] = l2r * tr - l2i * ti;
+      bt[2 * e + 1] = l2r * ti + l2i * tr;
+    }
+  };
+
+  {  // prologue: the last block (the only one that may be partial)
+    const int k0 = (nblk - 1) * NB, nk = sx - k0;
+    tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
+    stage_tb(0, k0, nk, (int)threadIdx.x, SWT);
+  }
+  __syncthreads();
+
+  for (int st = 0; st < nblk; ++st) {
+    // Thread indices re-derived each step from an opaque copy: otherwise the
+    // compiler hoists every per-thread address of the tile copies out of the
+    // loop and keeps them all live, which spills the solve's registers.
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int cur = st & 1, nxt = cur ^ 1;
+    const int kb = nblk - 1 - st, k0 = kb * NB, nk = min(NB, sx - k0), kend = k0 + nk;
+    T* cre = tiles + cur * TS;
+    T* cim = cre + NB * ldy;
+    T* nre = tiles + nxt * TS;
+    T* nim = nre + NB * ldy;
+    const int k0n = k0 - NB;   // next block (always full) when kb > 0
+    typename MF::acc_t acc[RB][NCB];
+    if (wave == 0) {
+      // ---- sequential solve of block kb -------------------------------
+      const bool active = lane < P;
+      const int p = lane % P;
+      const Cx<T> ca = active ? Cx<T>{(T)(l2.x * lo), (T)(l2.y * lo)} : cz<T>();
+      const Cx<T> cc = active ? Cx<T>{(T)(l2.x * up), (T)(l2.y * up)} : cz<T>();
+      const Cx<T>* tbc = reinterpret_cast<const Cx<T>*>(tbs + cur * 2 * NB * NB);
+      const T* lun = lu + (int64_t)n * sx * sy * 2;
+      auto load_inv = [&](int q, Cx<T> (&iv)[R]) {
+        const T* src = lun + ((int64_t)(k0 + q) * sy + p * R) * 2;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
+      };
+      Cx<T> d[NB][R];
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int idx = q * ldy + p * (R + 1) + i;
+          d[q][i] = (active && q < nk) ? Cx<T>{cre[idx], cim[idx]} : cz<T>();
+        }
+      Cx<T> ivn[R];
+      load_inv(nk - 1, ivn);
+#pragma unroll
+      for (int q = NB - 1; q >= 0; --q) {
+        if (q < nk) {
+          Cx<T> iv[R];
+#pragma unroll
+          for (int i = 0; i < R; ++i) iv[i] = ivn[i];
+          if (q > 0) load_inv(q - 1, ivn);
+          lu_scan_dpp<T, R, P>(d[q], iv, ca, cc, sy, lane);
+#pragma unroll
+          for (int qa = 0; qa < q; ++qa) {
+            const Cx<T> t = tbc[qa * NB + q];
+#pragma unroll
+            for (int i = 0; i < R; ++i) d[qa][i] = sub(d[qa][i], mul(t, d[q][i]));
+          }
+        }
+      }
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const int idx = q * ldy + p * (R + 1) + i;
+            if (q < nk) {
+              cre[idx] = d[q][i].x;
+              cim[idx] = d[q][i].y;
+            }
+          }
+      }
+    } else if (kb > 0) {
+      // ---- next block: stage its tile, coupling to the modes >= kend -----
+      const int ct = tid - 64, cw = wave - 1;
+      if (VEC) tile_load_vec<T, NB, R * P>(slice, nre, nim, k0n, sx, sy, ldy, R, ct, SWT - 64);
+      else tile_load_by(slice, nre, nim, k0n, NB, NB, sx, sy, ldy, R, ct, SWT - 64);
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+      coupling_far<T, NB, RB, VEC>(slice, tre, tim, sx, sy, k0n, kend, cw, lr, lk, acc);
+    }
+    __syncthreads();   // block kb solved in LDS; next tile staged
+    if (wave != 0 && kb > 0) {
+      const int ct = tid - 64, cw = wave - 1;
+      coupling_lds<T, NB, RB, R>(cre, cim, tre, tim, sx, sy, ldy, k0n, k0, nk, cw, lr, lk, acc);
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = cw * RB * 16 + i * 16 + MF::row(lk, v);
+          T cr, ci;
+          if constexpr (NCB == 2) {
+            cr = acc[i][0][v];
+            ci = acc[i][1][v];
+          } else {
+            cr = acc[i][0][v];
+            ci = __shfl_down(acc[i][0][v], 8, 16);   // imaginary part from lane lr + 8
+          }
+          if (y < sy && (NCB == 2 || lr < 8)) {
+            const int idx = lidx(lr, y, ldy, R);
+            nre[idx] -= l2r * cr - l2i * ci;
+            nim[idx] -= l2r * ci + l2i * cr;
+          }
+        }
+      stage_tb(nxt, k0n, NB, ct, SWT - 64);
+    }
+    if (VEC && nk == NB) tile_store_vec<T, NB, R * P>(slice, cre, cim, k0, sx, sy, ldy, R, tid, SWT);
+    else tile_store_by(slice, cre, cim, k0, nk, NB, sx, sy, ldy, R, tid, SWT);
+    __syncthreads();   // block kb in global memory; next tile and its T block ready
+  }
+}
+
 template <typename T, int R, int P, int NB, int BK, int RB, bool VEC>
-__global__ __launch_bounds__(NT, 2) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
+__global__ __launch_bounds__(NT, 2) void k_schur_sweep_wide(T* __restrict__ spec, const double2* __restrict__ lam,
                                                     const double2* __restrict__ tk,
                                                     const T* __restrict__ tup,
                                                     const T* __restrict__ lu, double lo, double di,
@@ -390,31 +759,75 @@ template <typename T, int R, int P, int NB, int BK, int RB>
 void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, BK>(pl);
-  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, BK, RB, true> : k_schur_sweep<T, R, P, NB, BK, RB, false>;
+  auto kfn = sh.vec ? k_schur_sweep_wide<T, R, P, NB, BK, RB, true> : k_schur_sweep_wide<T, R, P, NB, BK, RB, false>;
   hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
   kfn<<<dim3(g.F, g.B), NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, (const T*)op.tup, (const T*)op.lu,
                                          op.lo, op.di, op.up, g.F, g.sx, g.sy, sh.ldy);
 }
 
-// (NB, BK) per precision and row count: wide blocks while the A staging fits
-// in registers, narrower ones for 512 rows.
+// Pipelined kernel: LDS bytes of two tiles and two coupling blocks.
+template <typename T, int NB>
+size_t piped_lds(const SweepShape& sh) {
+  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)4 * NB * NB);
+}
+
+template <typename T, int R, int P, int NB, int RB>
+void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
+  const Geom& g = pl.g;
+  SweepShape sh = sweep_shape<T, NB, 16>(pl);
+  const size_t lds = piped_lds<T, NB>(sh);
+  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true> : k_schur_sweep<T, R, P, NB, RB, false>;
+  hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
+                                       g.F, g.sx, g.sy, sh.ldy);
+}
+
+// (NB, BK) of the wide kernel per precision and row count.
 template <typename T> struct SweepCfg;
 template <> struct SweepCfg<float> { static constexpr int NB = 16, BK = 32, NB8 = 8, BK8 = 16; };
 template <> struct SweepCfg<double> { static constexpr int NB = 8, BK = 16, NB8 = 8, BK8 = 16; };
 
+// Modes per block of the pipelined kernel: the block's lines live in wave 0's
+// registers (NB x R complex values per lane).
+template <typename T> struct PipedCfg;
+template <> struct PipedCfg<float> { static constexpr int NB4 = 16, NB8 = 8; };
+template <> struct PipedCfg<double> { static constexpr int NB4 = 0, NB8 = 0; };
+
+// float64 keeps the one-phase kernel: its coupling product (half the float32
+// MFMA rate) is the long pole, and there all four waves run it.
+
 template <typename T>
 void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   using C = SweepCfg<T>;
+  using PC = PipedCfg<T>;
   SweepShape sh = sweep_shape<T, C::NB, C::BK>(pl);
+  if constexpr (PC::NB8 > 0) {   // float32: pipelined kernel
+    // row blocks per coupling wave by line length: <= 64 rows: 2 (4 blocks),
+    // <= 128: 3 (8 blocks), <= 256: 6 (16 blocks), <= 512: 11 (32 blocks)
+#define PD_PIPED(RR, PP, BB, NBV)                                                         \
+  if (sh.R == RR && sh.P == PP) {                                                         \
+    launch_piped<T, RR, PP, NBV, BB>(pl, op, spec, s);                                    \
+    return;                                                                               \
+  }
+    PD_PIPED(4, 1, 2, PC::NB4) PD_PIPED(4, 2, 2, PC::NB4) PD_PIPED(4, 4, 2, PC::NB4)
+    PD_PIPED(4, 8, 2, PC::NB4) PD_PIPED(4, 16, 2, PC::NB4) PD_PIPED(4, 32, 3, PC::NB4)
+    PD_PIPED(4, 64, 6, PC::NB4)
+    PD_PIPED(8, 64, 11, PC::NB8)
+#undef PD_PIPED
+    return;
+  }
+  // float64: the one-phase kernel (block in LDS, coupling on all four waves)
+  if constexpr (PC::NB8 == 0) {
 #define PD_SWEEP(RR, PP, BB)                                                              \
   if (sh.R == RR && sh.P == PP && sh.RB == BB) {                                          \
     launch_one<T, RR, PP, C::NB, C::BK, BB>(pl, op, spec, s);                             \
     return;                                                                               \
   }
-  PD_SWEEP(4, 1, 1) PD_SWEEP(4, 2, 1) PD_SWEEP(4, 4, 1) PD_SWEEP(4, 8, 1) PD_SWEEP(4, 16, 1)
-  PD_SWEEP(4, 32, 2) PD_SWEEP(4, 64, 4)
+    PD_SWEEP(4, 1, 1) PD_SWEEP(4, 2, 1) PD_SWEEP(4, 4, 1) PD_SWEEP(4, 8, 1) PD_SWEEP(4, 16, 1)
+    PD_SWEEP(4, 32, 2) PD_SWEEP(4, 64, 4)
 #undef PD_SWEEP
-  if (sh.R == 8 && sh.P == 64 && sh.RB == 8) launch_one<T, 8, 64, C::NB8, C::BK8, 8>(pl, op, spec, s);
+    if (sh.R == 8 && sh.P == 64 && sh.RB == 8) launch_one<T, 8, 64, C::NB8, C::BK8, 8>(pl, op, spec, s);
+  }
 }
 
 }  // namespace
@@ -425,7 +838,7 @@ size_t schur_sweep_lds(const Plan& pl) {
     return a.RB == 8 ? sweep_shape<double, SweepCfg<double>::NB8, SweepCfg<double>::BK8>(pl).lds : a.lds;
   }
   SweepShape a = sweep_shape<float, 16, 32>(pl);
-  return a.RB == 8 ? sweep_shape<float, SweepCfg<float>::NB8, SweepCfg<float>::BK8>(pl).lds : a.lds;
+  return a.R == 4 ? piped_lds<float, PipedCfg<float>::NB4>(a) : piped_lds<float, PipedCfg<float>::NB8>(a);
 }
 
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {

@@ -112,24 +112,25 @@ constexpr int NT = 256;
 // Padded LDS index of row y of mode column k.
 __device__ __forceinline__ int lidx(int k, int y, int ldy, int R) { return k * ldy + y + y / R; }
 
-// Global -> LDS copy of a tile of TK mode columns by sy rows.  Loads are
-// issued in batches of 8 per thread before their LDS stores, so each thread
-// has several loads in flight instead of one load-wait-store chain.
+// Global -> LDS copy of a tile of TK mode columns by sy rows, by threads
+// t = 0..nthr-1.  Loads are issued in batches of 8 per thread before their LDS
+// stores, so each thread has several loads in flight instead of one
+// load-wait-store chain.
 template <typename T>
-__device__ void tile_load(const T* slice, T* sre, T* sim, int k0, int nk, int TK, int sx, int sy,
-                          int ldy, int R) {
+__device__ void tile_load_by(const T* slice, T* sre, T* sim, int k0, int nk, int TK, int sx, int sy,
+                             int ldy, int R, int t, int nthr) {
   const int total = sy * 2 * TK;
-  for (int base = 0; base < total; base += 8 * NT) {
+  for (int base = 0; base < total; base += 8 * nthr) {
     T v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      int e = base + u * NT + threadIdx.x;
+      int e = base + u * nthr + t;
       int k = e % TK, comp = (e / TK) & 1, y = e / (2 * TK);
       v[u] = (e < total && k < nk) ? slice[(int64_t)y * 2 * sx + comp * sx + k0 + k] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      int e = base + u * NT + threadIdx.x;
+      int e = base + u * nthr + t;
       int k = e % TK, comp = (e / TK) & 1, y = e / (2 * TK);
       if (e < total) (comp ? sim : sre)[lidx(k, y, ldy, R)] = v[u];
     }
@@ -137,12 +138,24 @@ __device__ void tile_load(const T* slice, T* sre, T* sim, int k0, int nk, int TK
 }
 
 template <typename T>
-__device__ void tile_store(T* slice, const T* sre, const T* sim, int k0, int nk, int TK, int sx,
-                           int sy, int ldy, int R) {
-  for (int e = threadIdx.x; e < sy * 2 * TK; e += NT) {
+__device__ void tile_store_by(T* slice, const T* sre, const T* sim, int k0, int nk, int TK, int sx,
+                              int sy, int ldy, int R, int t, int nthr) {
+  for (int e = t; e < sy * 2 * TK; e += nthr) {
     int k = e % TK, comp = (e / TK) & 1, y = e / (2 * TK);
     if (k < nk) slice[(int64_t)y * 2 * sx + comp * sx + k0 + k] = (comp ? sim : sre)[lidx(k, y, ldy, R)];
   }
+}
+
+template <typename T>
+__device__ void tile_load(const T* slice, T* sre, T* sim, int k0, int nk, int TK, int sx, int sy,
+                          int ldy, int R) {
+  tile_load_by(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R, (int)threadIdx.x, NT);
+}
+
+template <typename T>
+__device__ void tile_store(T* slice, const T* sre, const T* sim, int k0, int nk, int TK, int sx,
+                           int sy, int ldy, int R) {
+  tile_store_by(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R, (int)threadIdx.x, NT);
 }
 
 // Solve the line of tile column k with this wave's segment (all lanes call).
@@ -239,6 +252,186 @@ __device__ void lu_scan_wave(Cx<T> (&d)[R], const Cx<T> (&inv)[R], Cx<T> a, Cx<T
     Cx<T> t = mul(de[i], xn);
     d[i] = Cx<T>{ga[i].x + t.x, ga[i].y + t.y};
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// The same substitutions with the cross-lane steps on DPP row shifts (a VALU
+// operand modifier, no LDS round trip) and readlane for the carries between
+// rows of 16 lanes.  Segment of P lanes (P <= 16: several segments per row;
+// P = 32, 64: two or four rows); only the lanes of a segment exchange data.
+
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, typename T> __device__ __forceinline__ Cx<T> dpp_c(Cx<T> v) {
+  return Cx<T>{dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y)};
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename T> __device__ __forceinline__ Cx<T> lane_read(Cx<T> v, int l) {
+  return Cx<T>{lane_read(v.x, l), lane_read(v.y, l)};
+}
+template <typename T> __device__ __forceinline__ Cx<T> fma_c(Cx<T> a, Cx<T> b, Cx<T> c) {
+  // a + b c
+  return Cx<T>{a.x + b.x * c.x - b.y * c.y, a.y + b.x * c.y + b.y * c.x};
+}
+
+// DPP move whose lanes without a source in their row keep `old`.
+template <int CTRL> __device__ __forceinline__ float dpp_keep(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_keep(double old, double v) {
+  const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Complex DPP move that brings in the identity map (A = 0, B = 1) where the
+// source lane lies outside the row: composing with it changes nothing, so
+// rows of 16 lanes scan without branches.
+template <int CTRL, typename T> __device__ __forceinline__ void dpp_affine(Cx<T>& A, Cx<T>& B, Cx<T>& Ap, Cx<T>& Bp) {
+  Ap = Cx<T>{dpp_keep<CTRL>((T)0, A.x), dpp_keep<CTRL>((T)0, A.y)};
+  Bp = Cx<T>{dpp_keep<CTRL>((T)1, B.x), dpp_keep<CTRL>((T)0, B.y)};
+}
+
+// One level of the inclusive affine scan toward higher lanes: lanes at
+// position >= O in their row segment compose with the lane O below.  Whole
+// rows (P >= 16) rely on the identity fill; segments inside a row select.
+template <int O, int W, typename T>
+__device__ __forceinline__ void scan_up_level(Cx<T>& A, Cx<T>& B, int pw) {
+  if constexpr (O < W) {
+    Cx<T> Ap, Bp;
+    dpp_affine<0x110 + O>(A, B, Ap, Bp);
+    const Cx<T> An = fma_c(A, B, Ap), Bn = mul(B, Bp);
+    if constexpr (W == 16) {
+      A = An;
+      B = Bn;
+    } else {
+      const bool take = pw >= O;
+      A = Cx<T>{take ? An.x : A.x, take ? An.y : A.y};
+      B = Cx<T>{take ? Bn.x : B.x, take ? Bn.y : B.y};
+    }
+  }
+}
+// ... and toward lower lanes (suffix): lanes with position + O < W.
+template <int O, int W, typename T>
+__device__ __forceinline__ void scan_down_level(Cx<T>& G, Cx<T>& D, int pw) {
+  if constexpr (O < W) {
+    Cx<T> Gn, Dn;
+    dpp_affine<0x100 + O>(G, D, Gn, Dn);
+    const Cx<T> Gc = fma_c(G, D, Gn), Dc = mul(D, Dn);
+    if constexpr (W == 16) {
+      G = Gc;
+      D = Dc;
+    } else {
+      const bool take = pw + O < W;
+      G = Cx<T>{take ? Gc.x : G.x, take ? Gc.y : G.y};
+      D = Cx<T>{take ? Dc.x : D.x, take ? Dc.y : D.y};
+    }
+  }
+}
+
+// lu_scan_wave with DPP exchanges.  d, inv: rows p*R .. p*R+R-1 of the line
+// of this lane's segment (p = lane % P); all 64 lanes call it.
+template <typename T, int R, int P>
+__device__ __forceinline__ void lu_scan_dpp(Cx<T> (&d)[R], const Cx<T> (&inv)[R], Cx<T> a, Cx<T> c,
+                                            int N, int lane) {
+  constexpr int W = P < 16 ? P : 16;   // lanes of a segment inside one row
+  constexpr int NR = P < 16 ? 1 : P / 16;
+  const int p = lane % P;
+  const int pw = P < 16 ? p : (lane & 15);
+  const int rs = P < 16 ? 0 : (p >> 4);   // row of the lane inside its segment
+  const int row0 = p * R;
+  // forward: d'_y = (d_y - a d'_{y-1}) inv_y, as d'_i = al_i + be_i (entering d')
+  Cx<T> al[R], be[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int y = row0 + i;
+    const Cx<T> ay = (y > 0 && y < N) ? a : cz<T>();
+    const Cx<T> iv = (y < N) ? inv[i] : c1<T>();
+    const Cx<T> dy = (y < N) ? d[i] : cz<T>();
+    if (i == 0) {
+      al[0] = mul(dy, iv);
+      be[0] = neg(mul(ay, iv));
+    } else {
+      al[i] = mul(sub(dy, mul(ay, al[i - 1])), iv);
+      be[i] = neg(mul(mul(ay, be[i - 1]), iv));
+    }
+  }
+  Cx<T> A = al[R - 1], B = be[R - 1];
+  scan_up_level<1, W>(A, B, pw);
+  scan_up_level<2, W>(A, B, pw);
+  scan_up_level<4, W>(A, B, pw);
+  scan_up_level<8, W>(A, B, pw);
+  Cx<T> carry_in = cz<T>();   // d' entering the first lane of this lane's row
+  if constexpr (NR > 1) {
+    Cx<T> run = cz<T>();
+#pragma unroll
+    for (int r = 0; r < NR - 1; ++r) {
+      const Cx<T> At = lane_read(A, 16 * r + 15), Bt = lane_read(B, 16 * r + 15);
+      run = fma_c(At, Bt, run);
+      if (rs == r + 1) carry_in = run;
+    }
+    A = fma_c(A, B, carry_in);
+  }
+  // d' entering this lane: the lane below in the row, else the row carry
+  // (zero at the start of a segment)
+  Cx<T> din = Cx<T>{dpp_keep<0x111>(carry_in.x, A.x), dpp_keep<0x111>(carry_in.y, A.y)};
+  if constexpr (P < 16) {
+    if (p == 0) din = cz<T>();
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) d[i] = fma_c(al[i], be[i], din);
+  // backward: x_y = d'_y - c inv_y x_{y+1} (no coupling beyond row N-1)
+  Cx<T> ga[R], de[R];
+#pragma unroll
+  for (int i = R - 1; i >= 0; --i) {
+    const int y = row0 + i;
+    const Cx<T> cy = (y < N - 1) ? mul(c, inv[i]) : cz<T>();
+    if (i == R - 1) {
+      ga[i] = d[i];
+      de[i] = neg(cy);
+    } else {
+      ga[i] = sub(d[i], mul(cy, ga[i + 1]));
+      de[i] = neg(mul(cy, de[i + 1]));
+    }
+  }
+  Cx<T> G = ga[0], D = de[0];
+  scan_down_level<1, W>(G, D, pw);
+  scan_down_level<2, W>(G, D, pw);
+  scan_down_level<4, W>(G, D, pw);
+  scan_down_level<8, W>(G, D, pw);
+  Cx<T> carry_dn = cz<T>();   // x at the first row of the next row of lanes
+  if constexpr (NR > 1) {
+    Cx<T> run = cz<T>();
+#pragma unroll
+    for (int r = NR - 2; r >= 0; --r) {
+      const Cx<T> Gt = lane_read(G, 16 * (r + 1)), Dt = lane_read(D, 16 * (r + 1));
+      run = fma_c(Gt, Dt, run);
+      if (rs == r) carry_dn = run;
+    }
+    G = fma_c(G, D, carry_dn);
+  }
+  Cx<T> xn = Cx<T>{dpp_keep<0x101>(carry_dn.x, G.x), dpp_keep<0x101>(carry_dn.y, G.y)};
+  if constexpr (P < 16) {
+    if (p == P - 1) xn = cz<T>();
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) d[i] = fma_c(ga[i], de[i], xn);
 }
 
 }  // namespace tri

@@ -6,7 +6,7 @@ Tolerances (relative, max-abs error over max-abs reference):
   cond(V) <= 1/alpha (eq2.13) and the spatial condition number.
 * float32 preconditioner: 2e-3 (u32 = 6e-8 times 1/alpha = 1e3 times the line
   system condition numbers of these shapes).
-* split bf16 x-transform (hi + lo parts, three products): as float32, 2e-3.
+* split bf16 x-transform (three bf16 parts, six products): as float32, 2e-3.
 * single bf16 x-transform: 5e-2 with the sine basis (u_bf16 = 3.9e-3 in each of the
   two transforms, amplified as above).  With a non-normal x factor the Schur
   basis carries that rounding through the back-substitution, whose coupling
