@@ -678,6 +678,12 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
   if (bytes < need) { set_error("workspace smaller than the device tables"); return PD_ERR_WORKSPACE; }
   hipStream_t s = (hipStream_t)stream;
   const Geom& g = pl->g;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      pl->num_cu = ncu;
+  }
   char* p = (char*)workspace;
   auto take = [&](size_t n) { char* r = p; p += align_up(n); return r; };
   std::vector<std::vector<char>> keep;

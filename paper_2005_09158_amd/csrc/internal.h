@@ -93,6 +93,7 @@ struct Plan {
   void* spec_b = nullptr;
   // solver scratch (start of the solver region)
   char* solver_base = nullptr;
+  int num_cu = 256;                // compute units of the bound device (persistent grids)
   StageTimer timer;
 };
 

@@ -126,8 +126,6 @@ template <typename T> struct FftTraits;
 template <> struct FftTraits<float> { static constexpr int EPT = 32; };
 template <> struct FftTraits<double> { static constexpr int EPT = 16; };
 
-// Loads in flight per thread while the time columns are staged into LDS.
-constexpr int LOAD_BATCH = 16;
 
 // Copies the Nt-entry twiddle table into LDS behind the data columns.
 template <typename C>
@@ -151,7 +149,8 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
                                                    const double* __restrict__ gam,
                                                    const double* __restrict__ bscale,
                                                    const typename V2<T>::t* __restrict__ tw, int Nt,
-                                                   int logNt, int S, int sx, int sy, int reverse) {
+                                                   int logNt, int S, int sx, int sy, int reverse,
+                                                   int gam_lds) {
   using C = typename V2<T>::t;
   constexpr int EPT = FftTraits<T>::EPT;
   constexpr int NCOL = TX / 2;           // complex columns: one per pair of real columns
@@ -165,29 +164,33 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
   const double* xb = x + (int64_t)b * Nt * S;
   const double sc = bscale ? bscale[b] : 1.0;
   const bool vec = (S & 1) == 0;
-  stage_twiddles(smtw, tw, Nt);
+  double* smg = reinterpret_cast<double*>(smtw + Nt);   // Gamma
   // 1. stage: lane j of a row reads real columns (2j, 2j+1) with one 16-byte
   //    load and stores them as the complex value r_2j + i r_2j+1 of column j.
+  //    A tile's loads fit one batch ((TX/2) Nt <= EPT NT), all issued before
+  //    the first is consumed.
   {
     const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
     const int s = s0 + 2 * j;
-    for (int n0 = 0; n0 < Nt; n0 += RPI * LOAD_BATCH) {
-      double2 v[LOAD_BATCH];
+    double2 v[EPT];
 #pragma unroll
-      for (int u = 0; u < LOAD_BATCH; ++u) {
-        const int n = n0 + r + u * RPI;
-        if (n < Nt) {
-          const int nsrc = reverse ? (Nt - 1 - n) : n;
-          v[u] = load_pair(xb + (int64_t)nsrc * S, s, S, vec);
-        }
+    for (int u = 0; u < EPT; ++u) {
+      const int n = r + u * RPI;
+      if (n < Nt) {
+        const int nsrc = reverse ? (Nt - 1 - n) : n;
+        v[u] = load_pair(xb + (int64_t)nsrc * S, s, S, vec);
       }
+    }
+    stage_twiddles(smtw, tw, Nt);
+    if (gam_lds)
+      for (int i = threadIdx.x; i < Nt; i += NT) smg[i] = gam[i];
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < LOAD_BATCH; ++u) {
-        const int n = n0 + r + u * RPI;
-        if (n < Nt) {
-          const double g = gam[n] * sc;
-          sm[j * ld + n] = C{(T)(v[u].x * g), (T)(v[u].y * g)};
-        }
+    for (int u = 0; u < EPT; ++u) {
+      const int n = r + u * RPI;
+      if (n < Nt) {
+        const double g = (gam_lds ? smg[n] : gam[n]) * sc;
+        sm[j * ld + n] = C{(T)(v[u].x * g), (T)(v[u].y * g)};
       }
     }
   }
@@ -257,11 +260,12 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
     const int y = s / sx, xx = s - y * sx;
     const int y1 = (s + 1) / sx, xx1 = (s + 1) - y1 * sx;
     C* col = sm + j * ld;
-    for (int k0 = 0; k0 < F; k0 += RPI * LOAD_BATCH) {
-      C a[LOAD_BATCH], bb[LOAD_BATCH];
+    constexpr int KU = EPT / 2 + 1;   // F <= KU * RPI: one batch
+    {
+      C a[KU], bb[KU];
 #pragma unroll
-      for (int u = 0; u < LOAD_BATCH; ++u) {
-        const int k = k0 + r + u * RPI;
+      for (int u = 0; u < KU; ++u) {
+        const int k = r + u * RPI;
         a[u] = C{0, 0};
         bb[u] = C{0, 0};
         if (k < F && s < S) {
@@ -280,8 +284,8 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
         }
       }
 #pragma unroll
-      for (int u = 0; u < LOAD_BATCH; ++u) {
-        const int k = k0 + r + u * RPI;
+      for (int u = 0; u < KU; ++u) {
+        const int k = r + u * RPI;
         if (k < F) {
           const C A = a[u], Bv = bb[u];
           if (k == 0 || k == half) {
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
   }
 }
 
-struct FftShape { int TX; size_t lds; };
+struct FftShape { int TX; size_t lds; bool gam_lds; };
 
 // Widest tile (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex
 // columns of Nt+1 entries plus the twiddle table -- lets two workgroups share
@@ -338,10 +342,14 @@ FftShape choose_shape(const Plan& pl) {
   const int ept = f64 ? FftTraits<double>::EPT : FftTraits<float>::EPT;
   const size_t budget = 79 * 1024;
   int TX = 32;
+  // columns and twiddles; the forward kernel adds the Gamma table when it
+  // fits beside them without narrowing the tile
   auto lds = [&](int tx) { return (size_t)(tx / 2) * (g.nt + 1) * csize + (size_t)g.nt * csize; };
   while (TX > 2 && (lds(TX) > budget || (int64_t)(TX / 2) * g.nt > (int64_t)ept * NT)) TX >>= 1;
   while (TX > 2 && TX / 2 >= g.S) TX >>= 1;  // no wider than the spatial extent needs
-  return FftShape{TX, lds(TX)};
+  const size_t with_gam = lds(TX) + (size_t)g.nt * sizeof(double);
+  const bool gam_lds = with_gam <= budget;
+  return FftShape{TX, gam_lds ? with_gam : lds(TX), gam_lds};
 }
 
 template <typename T>
@@ -357,7 +365,7 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
     hipFuncSetAttribute((const void*)k_fft_fwd<T, W>,                                      \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
     k_fft_fwd<T, W><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt, logNt,   \
-                                             (int)g.S, g.sx, g.sy, reverse);               \
+                                             (int)g.S, g.sx, g.sy, reverse, sh.gam_lds);   \
     break;
   switch (sh.TX) {
     PD_FWD(2) PD_FWD(4) PD_FWD(8) PD_FWD(16) PD_FWD(32)

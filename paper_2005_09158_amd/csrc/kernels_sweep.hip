@@ -216,111 +216,60 @@ __device__ __forceinline__ void coupling_far(const T* slice, const T* tre, const
 
 // Coupling of the next block to the block just solved, with the solved lines
 // read from the LDS tile (lane group lk owns tile columns 4 lk .. 4 lk + 3,
-// the same permuted k order as coupling_direct).
-template <typename T, int NB, int RB, int R>
-__device__ __forceinline__ void coupling_lds(const T* sre, const T* sim, const T* tre, const T* tim,
-                                             int sx, int sy, int ldy, int k0n, int k0, int nk,
-                                             int cw, int lr, int lk,
-                                             typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
-  using MF = SweepMfma<T>;
+// the same permuted k order as coupling_direct).  NB <= 16: one 16-column
+// step.  The T entries (rows of the next block, columns of the solved block)
+// are loaded ahead by near_t.
+template <typename T, int NB>
+__device__ __forceinline__ void near_t(T (&trv)[4], T (&tiv)[4], const T* tre, const T* tim, int sx,
+                                       int k0n, int k0, int nk, int lr, int lk) {
   constexpr int NCB = 2 * NB / 16;
   const int q = (NCB == 2) ? lr : (lr & 7);
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int jj = 4 * lk + st;
+    const bool ok = jj < nk;
+    trv[st] = ok ? tre[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
+    tiv[st] = ok ? tim[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
+  }
+}
+
+template <typename T, int NB, int RB, int R>
+__device__ __forceinline__ void coupling_lds(const T* sre, const T* sim, const T (&trv)[4],
+                                             const T (&tiv)[4], int sy, int ldy, int nk, int cw,
+                                             int lr, int lk,
+                                             typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+  static_assert(NB <= 16, "one 16-column step");
+  using MF = SweepMfma<T>;
+  constexpr int NCB = 2 * NB / 16;
   const int part = (NCB == 2) ? 0 : (lr >> 3);
   const int r0 = cw * RB * 16 + lr;
+  T av_r[RB][4], av_i[RB][4];
 #pragma unroll
-  for (int jb = 0; jb < NB; jb += 16) {
-    T trv[4], tiv[4];
-    T av_r[RB][4], av_i[RB][4];
+  for (int st = 0; st < 4; ++st) {
+    const int jj = 4 * lk + st;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int jj = jb + 4 * lk + st;
-      const bool ok = jj < nk;
-      trv[st] = ok ? tre[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
-      tiv[st] = ok ? tim[(int64_t)(k0n + q) * sx + k0 + jj] : (T)0;
+    for (int i = 0; i < RB; ++i) {
+      const int y = r0 + 16 * i;
+      const bool rok = jj < nk && y < sy;
+      av_r[i][st] = rok ? sre[lidx(jj, y, ldy, R)] : (T)0;
+      av_i[i][st] = rok ? sim[lidx(jj, y, ldy, R)] : (T)0;
+    }
+  }
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int y = r0 + 16 * i;
-        const bool rok = ok && y < sy;
-        av_r[i][st] = rok ? sre[lidx(jj, y, ldy, R)] : (T)0;
-        av_i[i][st] = rok ? sim[lidx(jj, y, ldy, R)] : (T)0;
+  for (int st = 0; st < 4; ++st) {
+    const T b_re_r = trv[st], b_re_i = -tiv[st], b_im_r = tiv[st], b_im_i = trv[st];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      if constexpr (NCB == 2) {
+        acc[i][0] = MF::run(av_r[i][st], b_re_r, acc[i][0]);
+        acc[i][0] = MF::run(av_i[i][st], b_re_i, acc[i][0]);
+        acc[i][1] = MF::run(av_r[i][st], b_im_r, acc[i][1]);
+        acc[i][1] = MF::run(av_i[i][st], b_im_i, acc[i][1]);
+      } else {
+        acc[i][0] = MF::run(av_r[i][st], part ? b_im_r : b_re_r, acc[i][0]);
+        acc[i][0] = MF::run(av_i[i][st], part ? b_im_i : b_re_i, acc[i][0]);
       }
     }
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const T b_re_r = trv[st], b_re_i = -tiv[st], b_im_r = tiv[st], b_im_i = trv[st];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        if constexpr (NCB == 2) {
-          acc[i][0] = MF::run(av_r[i][st], b_re_r, acc[i][0]);
-          acc[i][0] = MF::run(av_i[i][st], b_re_i, acc[i][0]);
-          acc[i][1] = MF::run(av_r[i][st], b_im_r, acc[i][1]);
-          acc[i][1] = MF::run(av_i[i][st], b_im_i, acc[i][1]);
-        } else {
-          acc[i][0] = MF::run(av_r[i][st], part ? b_im_r : b_re_r, acc[i][0]);
-          acc[i][0] = MF::run(av_i[i][st], part ? b_im_i : b_re_i, acc[i][0]);
-        }
-      }
-    }
-  }
-}
-
-// 16-byte copies of a full tile (NB modes, sx % 4 == 0): each vector holds
-// MV consecutive modes of one row part; every thread issues all its loads
-// before its LDS stores.  MAXROWS bounds sy.
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using t = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using t = double2; static constexpr int n = 2; };
-
-template <typename T> __device__ __forceinline__ T vget(const float4& v, int m) {
-  return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
-}
-template <typename T> __device__ __forceinline__ T vget(const double2& v, int m) {
-  return m == 0 ? v.x : v.y;
-}
-
-template <typename T, int NB, int MAXROWS>
-__device__ __forceinline__ void tile_load_vec(const T* slice, T* sre, T* sim, int k0, int sx, int sy,
-                                              int ldy, int R, int t, int nthr) {
-  using V = typename Vec16<T>::t;
-  constexpr int MV = Vec16<T>::n, NV = NB / MV;
-  constexpr int MAXE = MAXROWS * 2 * NV;
-  constexpr int MAXU = (MAXE + 191) / 192;   // nthr >= 192
-  const int total = sy * 2 * NV;
-  V v[MAXU];
-#pragma unroll
-  for (int u = 0; u < MAXU; ++u) {
-    const int e = t + u * nthr;
-    if (e < total) {
-      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
-      v[u] = *reinterpret_cast<const V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < MAXU; ++u) {
-    const int e = t + u * nthr;
-    if (e < total) {
-      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
-      T* dst = comp ? sim : sre;
-#pragma unroll
-      for (int m = 0; m < MV; ++m) dst[lidx(kv * MV + m, y, ldy, R)] = vget<T>(v[u], m);
-    }
-  }
-}
-
-template <typename T, int NB, int MAXROWS>
-__device__ __forceinline__ void tile_store_vec(T* slice, const T* sre, const T* sim, int k0, int sx,
-                                               int sy, int ldy, int R, int t, int nthr) {
-  using V = typename Vec16<T>::t;
-  constexpr int MV = Vec16<T>::n, NV = NB / MV;
-  const int total = sy * 2 * NV;
-  for (int e = t; e < total; e += nthr) {
-    const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
-    const T* src = comp ? sim : sre;
-    V v;
-    T* vv = reinterpret_cast<T*>(&v);
-#pragma unroll
-    for (int m = 0; m < MV; ++m) vv[m] = src[lidx(kv * MV + m, y, ldy, R)];
-    *reinterpret_cast<V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV) = v;
   }
 }
 
@@ -393,6 +342,7 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
     T* nim = nre + NB * ldy;
     const int k0n = k0 - NB;   // next block (always full) when kb > 0
     typename MF::acc_t acc[RB][NCB];
+    T tn_r[4], tn_i[4];        // T entries of the near coupling
     if (wave == 0) {
       // ---- sequential solve of block kb -------------------------------
       const bool active = lane < P;
@@ -427,9 +377,14 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
           lu_scan_dpp<T, R, P>(d[q], iv, ca, cc, sy, lane);
 #pragma unroll
           for (int qa = 0; qa < q; ++qa) {
+            // d_qa -= t w_q, in four fused multiply-adds per complex value
             const Cx<T> t = tbc[qa * NB + q];
 #pragma unroll
-            for (int i = 0; i < R; ++i) d[qa][i] = sub(d[qa][i], mul(t, d[q][i]));
+            for (int i = 0; i < R; ++i) {
+              const Cx<T> w = d[q][i];
+              d[qa][i].x = fma(-t.x, w.x, fma(t.y, w.y, d[qa][i].x));
+              d[qa][i].y = fma(-t.x, w.y, fma(-t.y, w.x, d[qa][i].y));
+            }
           }
         }
       }
@@ -448,7 +403,7 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
     } else if (kb > 0) {
       // ---- next block: stage its tile, coupling to the modes >= kend -----
       const int ct = tid - 64, cw = wave - 1;
-      if (VEC) tile_load_vec<T, NB, R * P>(slice, nre, nim, k0n, sx, sy, ldy, R, ct, SWT - 64);
+      if (VEC) tile_load_vec<T, NB, R * P, SWT - 64>(slice, nre, nim, k0n, sx, sy, ldy, R, ct, SWT - 64);
       else tile_load_by(slice, nre, nim, k0n, NB, NB, sx, sy, ldy, R, ct, SWT - 64);
 #pragma unroll
       for (int i = 0; i < RB; ++i)
@@ -457,11 +412,15 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
       coupling_far<T, NB, RB, VEC>(slice, tre, tim, sx, sy, k0n, kend, cw, lr, lk, acc);
+      // ahead of the barrier: the next block's in-block coefficients and the
+      // T entries of its coupling to the block being solved
+      stage_tb(nxt, k0n, NB, ct, SWT - 64);
+      near_t<T, NB>(tn_r, tn_i, tre, tim, sx, k0n, k0, nk, lr, lk);
     }
     __syncthreads();   // block kb solved in LDS; next tile staged
     if (wave != 0 && kb > 0) {
-      const int ct = tid - 64, cw = wave - 1;
-      coupling_lds<T, NB, RB, R>(cre, cim, tre, tim, sx, sy, ldy, k0n, k0, nk, cw, lr, lk, acc);
+      const int cw = wave - 1;
+      coupling_lds<T, NB, RB, R>(cre, cim, tn_r, tn_i, sy, ldy, nk, cw, lr, lk, acc);
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -481,7 +440,6 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
             nim[idx] -= l2r * ci + l2i * cr;
           }
         }
-      stage_tb(nxt, k0n, NB, ct, SWT - 64);
     }
     if (VEC && nk == NB) tile_store_vec<T, NB, R * P>(slice, cre, cim, k0, sx, sy, ldy, R, tid, SWT);
     else tile_store_by(slice, cre, cim, k0, nk, NB, sx, sy, ldy, R, tid, SWT);

@@ -30,8 +30,10 @@ namespace {
 
 using namespace tri;
 
-// Independent lines (1D, or 2D with a diagonal x-mode matrix T).
-template <typename T, int R, int P>
+// Independent lines (1D, or 2D with a diagonal x-mode matrix T).  TKV > 0:
+// tiles of TKV modes copied with 16-byte vectors (sx % 4 == 0), the last
+// partial tile element-wise; TKV = 0: element-wise copies of TK modes.
+template <typename T, int R, int P, int TKV>
 __global__ __launch_bounds__(NT) void k_line_solve(T* __restrict__ spec, const double2* __restrict__ lam,
                                                    const double2* __restrict__ tk, double lo, double di,
                                                    double up, int F, int sx, int sy, int TK, int ldy) {
@@ -41,7 +43,14 @@ __global__ __launch_bounds__(NT) void k_line_solve(T* __restrict__ spec, const d
   const int k0 = blockIdx.x * TK, n = blockIdx.y, b = blockIdx.z;
   const int nk = min(TK, sx - k0);
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
-  tile_load(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  bool vec = false;
+  if constexpr (TKV > 0) vec = nk == TKV;
+  if constexpr (TKV > 0) {
+    if (vec) tile_load_vec<T, TKV, R * P, NT>(slice, sre, sim, k0, sx, sy, ldy, R, (int)threadIdx.x, NT);
+    else tile_load(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  } else {
+    tile_load(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  }
   __syncthreads();
   constexpr int LW = 64 / P;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -59,7 +68,12 @@ __global__ __launch_bounds__(NT) void k_line_solve(T* __restrict__ spec, const d
     solve_tile_line<T, R, P>(sre, sim, k, active, ca, cb, cc, sy, ldy, p);
   }
   __syncthreads();
-  tile_store(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  if constexpr (TKV > 0) {
+    if (vec) tile_store_vec<T, TKV, R * P>(slice, sre, sim, k0, sx, sy, ldy, R, (int)threadIdx.x, NT);
+    else tile_store(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  } else {
+    tile_store(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R);
+  }
 }
 
 struct LineShape { int R, P, TK, ldy; size_t lds; };
@@ -84,17 +98,25 @@ void launch_lines(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   LineShape sh = line_shape(pl);
   dim3 grid((g.sx + sh.TK - 1) / sh.TK, g.F, g.B);
+  const bool vec = (g.sx % 4) == 0;
+#define PD_LINE_K(RR, PP, TKV)                                                                    \
+  {                                                                                               \
+    hipFuncSetAttribute((const void*)k_line_solve<T, RR, PP, TKV>,                                \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);                 \
+    k_line_solve<T, RR, PP, TKV><<<grid, NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, op.lo, op.di,    \
+                                                          op.up, g.F, g.sx, g.sy, sh.TK, sh.ldy); \
+    return;                                                                                       \
+  }
 #define PD_LINE(RR, PP)                                                                           \
   if (sh.R == RR && sh.P == PP) {                                                                 \
-    hipFuncSetAttribute((const void*)k_line_solve<T, RR, PP>,                                     \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);                 \
-    k_line_solve<T, RR, PP><<<grid, NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, op.lo, op.di, op.up,  \
-                                                     g.F, g.sx, g.sy, sh.TK, sh.ldy);             \
-    return;                                                                                       \
+    if (vec && sh.TK == 16) PD_LINE_K(RR, PP, 16)                                                 \
+    if (vec && sh.TK == 8) PD_LINE_K(RR, PP, 8)                                                   \
+    PD_LINE_K(RR, PP, 0)                                                                          \
   }
   PD_LINE(4, 1) PD_LINE(4, 2) PD_LINE(4, 4) PD_LINE(4, 8) PD_LINE(4, 16) PD_LINE(4, 32)
   PD_LINE(4, 64) PD_LINE(8, 64) PD_LINE(16, 64) PD_LINE(32, 64)
 #undef PD_LINE
+#undef PD_LINE_K
 }
 
 }  // namespace

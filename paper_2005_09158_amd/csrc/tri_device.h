@@ -158,6 +158,67 @@ __device__ void tile_store(T* slice, const T* sre, const T* sim, int k0, int nk,
   tile_store_by(slice, sre, sim, k0, nk, TK, sx, sy, ldy, R, (int)threadIdx.x, NT);
 }
 
+// 16-byte copies of a full tile (NB modes, sx % 4 == 0, k0 % 4 == 0): each
+// vector holds MV consecutive modes of one row part; every thread issues all
+// its loads before its LDS stores.  MAXROWS bounds sy, MINTHR bounds nthr
+// from below.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using t = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using t = double2; static constexpr int n = 2; };
+
+template <typename T> __device__ __forceinline__ T vget(const float4& v, int m) {
+  return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
+}
+template <typename T> __device__ __forceinline__ T vget(const double2& v, int m) {
+  return m == 0 ? v.x : v.y;
+}
+
+template <typename T, int NB, int MAXROWS, int MINTHR>
+__device__ __forceinline__ void tile_load_vec(const T* slice, T* sre, T* sim, int k0, int sx, int sy,
+                                              int ldy, int R, int t, int nthr) {
+  using V = typename Vec16<T>::t;
+  constexpr int MV = Vec16<T>::n, NV = NB / MV;
+  constexpr int MAXE = MAXROWS * 2 * NV;
+  constexpr int MAXU = (MAXE + MINTHR - 1) / MINTHR;   // nthr >= MINTHR
+  const int total = sy * 2 * NV;
+  V v[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = t + u * nthr;
+    if (e < total) {
+      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+      v[u] = *reinterpret_cast<const V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = t + u * nthr;
+    if (e < total) {
+      const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+      T* dst = comp ? sim : sre;
+#pragma unroll
+      for (int m = 0; m < MV; ++m) dst[lidx(kv * MV + m, y, ldy, R)] = vget<T>(v[u], m);
+    }
+  }
+}
+
+template <typename T, int NB, int MAXROWS>
+__device__ __forceinline__ void tile_store_vec(T* slice, const T* sre, const T* sim, int k0, int sx,
+                                               int sy, int ldy, int R, int t, int nthr) {
+  using V = typename Vec16<T>::t;
+  constexpr int MV = Vec16<T>::n, NV = NB / MV;
+  const int total = sy * 2 * NV;
+  for (int e = t; e < total; e += nthr) {
+    const int kv = e % NV, comp = (e / NV) & 1, y = e / (2 * NV);
+    const T* src = comp ? sim : sre;
+    V v;
+    T* vv = reinterpret_cast<T*>(&v);
+#pragma unroll
+    for (int m = 0; m < MV; ++m) vv[m] = src[lidx(kv * MV + m, y, ldy, R)];
+    *reinterpret_cast<V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV) = v;
+  }
+}
+
 // Solve the line of tile column k with this wave's segment (all lanes call).
 template <typename T, int R, int P>
 __device__ void solve_tile_line(T* sre, T* sim, int k, bool active, Cx<T> a, Cx<T> b, Cx<T> c,
@@ -356,20 +417,24 @@ __device__ __forceinline__ void lu_scan_dpp(Cx<T> (&d)[R], const Cx<T> (&inv)[R]
   const int pw = P < 16 ? p : (lane & 15);
   const int rs = P < 16 ? 0 : (p >> 4);   // row of the lane inside its segment
   const int row0 = p * R;
-  // forward: d'_y = (d_y - a d'_{y-1}) inv_y, as d'_i = al_i + be_i (entering d')
+  // forward: d'_y = inv_y d_y + e_y d'_{y-1} with e_y = -a inv_y, as
+  // d'_i = al_i + be_i (entering d'); e and be do not depend on the data and
+  // run beside the al chain
   Cx<T> al[R], be[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int y = row0 + i;
-    const Cx<T> ay = (y > 0 && y < N) ? a : cz<T>();
     const Cx<T> iv = (y < N) ? inv[i] : c1<T>();
     const Cx<T> dy = (y < N) ? d[i] : cz<T>();
+    const Cx<T> na = (y > 0 && y < N) ? neg(a) : cz<T>();
+    const Cx<T> e = mul(na, iv);
+    const Cx<T> f = mul(dy, iv);
     if (i == 0) {
-      al[0] = mul(dy, iv);
-      be[0] = neg(mul(ay, iv));
+      al[0] = f;
+      be[0] = e;
     } else {
-      al[i] = mul(sub(dy, mul(ay, al[i - 1])), iv);
-      be[i] = neg(mul(mul(ay, be[i - 1]), iv));
+      al[i] = fma_c(f, e, al[i - 1]);
+      be[i] = mul(e, be[i - 1]);
     }
   }
   Cx<T> A = al[R - 1], B = be[R - 1];
@@ -396,18 +461,20 @@ __device__ __forceinline__ void lu_scan_dpp(Cx<T> (&d)[R], const Cx<T> (&inv)[R]
   }
 #pragma unroll
   for (int i = 0; i < R; ++i) d[i] = fma_c(al[i], be[i], din);
-  // backward: x_y = d'_y - c inv_y x_{y+1} (no coupling beyond row N-1)
+  // backward: x_y = d'_y + g_y x_{y+1}, g_y = -c inv_y (no coupling beyond
+  // row N-1)
   Cx<T> ga[R], de[R];
+  const Cx<T> nc = neg(c);
 #pragma unroll
   for (int i = R - 1; i >= 0; --i) {
     const int y = row0 + i;
-    const Cx<T> cy = (y < N - 1) ? mul(c, inv[i]) : cz<T>();
+    const Cx<T> g = (y < N - 1) ? mul(nc, inv[i]) : cz<T>();
     if (i == R - 1) {
       ga[i] = d[i];
-      de[i] = neg(cy);
+      de[i] = g;
     } else {
-      ga[i] = sub(d[i], mul(cy, ga[i + 1]));
-      de[i] = neg(mul(cy, de[i + 1]));
+      ga[i] = fma_c(d[i], g, ga[i + 1]);
+      de[i] = mul(g, de[i + 1]);
     }
   }
   Cx<T> G = ga[0], D = de[0];

@@ -64,6 +64,27 @@ def test_precond_parity(case, prec):
     assert err < tol
 
 
+# Back-sweep shapes: every line-segment width of the one-wave scan (rows per
+# line 3 .. 128 -> 1 .. 32 lanes), a partial last block of modes, and
+# x-sizes that are not multiples of 4 (scalar coupling loads).
+SWEEP_SHAPES = [(20, 3), (21, 7), (36, 13), (37, 100), (48, 128), (17, 33)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny", SWEEP_SHAPES)
+def test_schur_sweep_shapes(nx, ny, prec):
+    announce(f"sweep shape {nx}x{ny} {prec}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nt=8, scheme="tr", T=0.5, nu=0.1, ax=1.0, ay=0.5, alpha=1e-2)
+    torch, pd, prob = make(cfg, prec)
+    r = np.random.default_rng(7).standard_normal((prob.nt, prob.nspace))
+    z_ref = o_prec.three_steps(prob, r)
+    z = pd.apply_precond(to_gpu(torch, r, pd.shape))
+    torch.cuda.synchronize()
+    err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
+    print(f"  rel err {err:.3e}")
+    assert err < PREC_TOL[prec]
+
+
 @pytest.mark.parametrize("case", ["1d-be", "2d-tr-schur", "2d-lf-dst", "2d-be-schur-ragged"])
 def test_precond_in_place_and_batch(case):
     announce(f"precond batch/in-place {case}")
