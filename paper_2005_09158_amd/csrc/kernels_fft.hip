@@ -40,11 +40,25 @@ template <typename C> __device__ __forceinline__ C cmi(C a) { return C{a.y, -a.x
 
 constexpr int NT = 256;
 
-// In-place forward Stockham FFT of `ncol` columns of length Nt (column stride
-// ld) in LDS.  EPT = complex values held per thread in a pass (>= ncol*Nt/NT).
-template <typename T, int EPT>
-__device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int ld, int Nt, int logNt,
-                            const typename V2<T>::t* __restrict__ tw) {
+// Column bases in LDS: a uniform stride, or the sub-columns of the four-step
+// kernels (column c = N1 j + q at j cstr + q ldc).
+struct ColUniform {
+  int ld;
+  __device__ __forceinline__ int base(int c) const { return c * ld; }
+};
+template <int LOGN1> struct ColSub {
+  int ldc, cstr;
+  __device__ __forceinline__ int base(int c) const {
+    return (c >> LOGN1) * cstr + (c & ((1 << LOGN1) - 1)) * ldc;
+  }
+};
+
+// In-place forward Stockham FFT of `ncol` columns of length Nt in LDS, column
+// c at sm + cm.base(c).  EPT = complex values held per thread in a pass
+// (>= ncol*Nt/NT).  tw[k * tws] = exp(-2 pi i k / Nt).
+template <typename T, int EPT, typename CM>
+__device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM cm, int Nt, int logNt,
+                                            const typename V2<T>::t* __restrict__ tw, int tws = 1) {
   using C = typename V2<T>::t;
   int Ns = 1;
   int bits = logNt;
@@ -56,7 +70,7 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int
       int bf = threadIdx.x + i * NT;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
-        const C* src = sm + col * ld + j;
+        const C* src = sm + cm.base(col) + j;
         v[2 * i] = src[0];
         v[2 * i + 1] = src[nb];
       }
@@ -68,7 +82,7 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
         // Ns == 1: no twiddle
-        C* dst = sm + col * ld + (j << 1);
+        C* dst = sm + cm.base(col) + (j << 1);
         dst[0] = cadd(v[2 * i], v[2 * i + 1]);
         dst[1] = csub(v[2 * i], v[2 * i + 1]);
       }
@@ -86,7 +100,7 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int
       int bf = threadIdx.x + i * NT;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
-        const C* src = sm + col * ld + j;
+        const C* src = sm + cm.base(col) + j;
         v[4 * i] = src[0];
         v[4 * i + 1] = src[nb];
         v[4 * i + 2] = src[2 * nb];
@@ -102,12 +116,12 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, int
         int k = j & (Ns - 1);
         C v0 = v[4 * i], v1 = v[4 * i + 1], v2 = v[4 * i + 2], v3 = v[4 * i + 3];
         if (k) {
-          v1 = cmul(v1, tw[k * step]);
-          v2 = cmul(v2, tw[2 * k * step]);
-          v3 = cmul(v3, tw[3 * k * step]);
+          v1 = cmul(v1, tw[k * step * tws]);
+          v2 = cmul(v2, tw[2 * k * step * tws]);
+          v3 = cmul(v3, tw[3 * k * step * tws]);
         }
         C t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = cmi(csub(v1, v3));
-        C* dst = sm + col * ld + ((j - k) << 2) + k;
+        C* dst = sm + cm.base(col) + ((j - k) << 2) + k;
         dst[0] = cadd(t0, t2);
         dst[Ns] = cadd(t1, t3);
         dst[2 * Ns] = csub(t0, t2);
@@ -195,7 +209,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
     }
   }
   __syncthreads();
-  fft_columns<T, EPT>(sm, NCOL, ld, Nt, logNt, smtw);
+  fft_columns<T, EPT>(sm, NCOL, ColUniform{ld}, Nt, logNt, smtw);
   // 2. Hermitian split of column j into the half spectra of real columns 2j
   //    and 2j+1, written as (re, re) and (im, im) pairs of adjacent x.
   T* specb = spec + (int64_t)b * F * sy * 2 * sx;
@@ -299,7 +313,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
     }
   }
   __syncthreads();
-  fft_columns<T, EPT>(sm, NCOL, ld, Nt, logNt, smtw);
+  fft_columns<T, EPT>(sm, NCOL, ColUniform{ld}, Nt, logNt, smtw);
   // 2. z = conj(fft(conj Z)) / Nt: real column 2j is Re, column 2j+1 is -Im;
   //    Gamma^{-1} (with the 1/Nt) in float64.
   if (s >= S) return;
@@ -330,7 +344,245 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
   }
 }
 
-struct FftShape { int TX; size_t lds; bool gam_lds; };
+// ---------------------------------------------------------------------------
+// Four-step form (Nt = N1 * TPC, TPC = NT / NCOL threads per column): thread
+// r of column j holds the samples n = r + TPC u (u < N1) -- exactly its global
+// loads -- and transforms them in registers,
+//   X_r[q] = sum_u x[r + TPC u] W_N1^{u q},  then  X_r[q] *= W_Nt^{r q};
+// the TPC-point transforms over r of every (j, q) then run as Stockham passes
+// in LDS, and Z[q + N1 p] is their output p.  Two LDS passes replace five at
+// Nt = 512 (three replace six at Nt = 2048).
+
+// In-register radix-2 decimation-in-frequency transform of N values; the
+// result is in bit-reversed order.  tw[k * tws] = exp(-2 pi i k / N).
+template <int N, typename C>
+__device__ __forceinline__ void reg_fft(C (&c)[N], const C* tw, int tws) {
+#pragma unroll
+  for (int len = N; len >= 2; len >>= 1) {
+    const int h = len >> 1;
+#pragma unroll
+    for (int i0 = 0; i0 < N; i0 += len)
+#pragma unroll
+      for (int t = 0; t < h; ++t) {
+        const C a = c[i0 + t], b = c[i0 + t + h];
+        c[i0 + t] = cadd(a, b);
+        const C d = csub(a, b);
+        const int e = t * (N / len);   // W_len^t = W_N^e
+        if (e == 0) c[i0 + t + h] = d;
+        else if (4 * e == N) c[i0 + t + h] = cmi(d);
+        else c[i0 + t + h] = cmul(d, tw[e * tws]);
+      }
+  }
+}
+
+template <int N> __device__ __forceinline__ constexpr int brev(int q) {
+  int r = 0;
+  for (int b = 1; b < N; b <<= 1) r = (r << 1) | ((q & b) ? 1 : 0);
+  return r;
+}
+
+template <int V> struct Log2 { static constexpr int v = 1 + Log2<V / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+// Pass 1 of the four-step form on this thread's pencil c (natural order in
+// u), twiddle, and store to the sub-column layout: (j, q) position r.
+template <typename T, int N1, int TPC>
+__device__ __forceinline__ void fourstep_pass1(typename V2<T>::t (&c)[N1], typename V2<T>::t* sm,
+                                               const typename V2<T>::t* smtw, int Nt, int j, int r,
+                                               int ldc, int cstr) {
+  using C = typename V2<T>::t;
+  reg_fft<N1>(c, smtw, Nt / N1);
+#pragma unroll
+  for (int q = 0; q < N1; ++q) {
+    C xq = c[brev<N1>(q)];
+    if (q) xq = cmul(xq, smtw[(r * q) & (Nt - 1)]);
+    sm[j * cstr + q * ldc + r] = xq;
+  }
+}
+
+template <typename T, int TX, int N1>
+__global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x, T* __restrict__ spec,
+                                                    const double* __restrict__ gam,
+                                                    const double* __restrict__ bscale,
+                                                    const typename V2<T>::t* __restrict__ tw, int Nt,
+                                                    int S, int sx, int sy, int reverse, int gam_lds,
+                                                    int tw_lds) {
+  using C = typename V2<T>::t;
+  constexpr int NCOL = TX / 2, TPC = NT / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
+  constexpr int LDC = TPC + 1;           // sub-column stride
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
+  const int cstr = N1 * LDC + 1;         // column stride (odd: columns fall in different banks)
+  const int F = (Nt >> 1) + 1;
+  C* smtw = sm + NCOL * cstr;
+  double* smg = reinterpret_cast<double*>(smtw + (tw_lds ? Nt : 0));
+  const C* twp = tw_lds ? smtw : tw;     // twiddles in LDS, or through the caches
+  const int b = blockIdx.y, s0 = blockIdx.x * TX;
+  const double* xb = x + (int64_t)b * Nt * S;
+  const double sc = bscale ? bscale[b] : 1.0;
+  const bool vec = (S & 1) == 0;
+  const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
+  const int s = s0 + 2 * j;
+  double2 v[N1];
+#pragma unroll
+  for (int u = 0; u < N1; ++u) {
+    const int n = r + TPC * u;
+    const int nsrc = reverse ? (Nt - 1 - n) : n;
+    v[u] = load_pair(xb + (int64_t)nsrc * S, s, S, vec);
+  }
+  if (tw_lds) stage_twiddles(smtw, tw, Nt);
+  if (gam_lds)
+    for (int i = threadIdx.x; i < Nt; i += NT) smg[i] = gam[i];
+  __syncthreads();
+  C c[N1];
+#pragma unroll
+  for (int u = 0; u < N1; ++u) {
+    const int n = r + TPC * u;
+    const double g = (gam_lds ? smg[n] : gam[n]) * sc;
+    c[u] = C{(T)(v[u].x * g), (T)(v[u].y * g)};
+  }
+  fourstep_pass1<T, N1, TPC>(c, sm, twp, Nt, j, r, LDC, cstr);
+  __syncthreads();
+  fft_columns<T, N1>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
+  // Hermitian split (as k_fft_fwd), Z[k] at (j, k mod N1) position k / N1
+  if (s >= S) return;
+  T* specb = spec + (int64_t)b * F * sy * 2 * sx;
+  const bool vout = (sx & 1) == 0;
+  const int y = s / sx, xx = s - y * sx;
+  const int y1 = (s + 1) / sx, xx1 = (s + 1) - y1 * sx;
+  const C* colj = sm + j * cstr;
+  for (int k = r; k < F; k += TPC) {
+    const int km = (Nt - k) & (Nt - 1);
+    const C zk = colj[(k & (N1 - 1)) * LDC + (k >> LOGN1)];
+    const C zm = colj[(km & (N1 - 1)) * LDC + (km >> LOGN1)];
+    const T ar = (T)0.5 * (zk.x + zm.x), ai = (T)0.5 * (zk.y - zm.y);
+    const T br = (T)0.5 * (zk.y + zm.y), bi = (T)0.5 * (zm.x - zk.x);
+    T* dst = specb + ((int64_t)k * sy + y) * 2 * sx + xx;
+    if (vout && s + 1 < S) {
+      *reinterpret_cast<C*>(dst) = C{ar, br};
+      *reinterpret_cast<C*>(dst + sx) = C{ai, bi};
+    } else {
+      dst[0] = ar;
+      dst[sx] = ai;
+      if (s + 1 < S) {
+        T* d1 = specb + ((int64_t)k * sy + y1) * 2 * sx + xx1;
+        d1[0] = br;
+        d1[sx] = bi;
+      }
+    }
+  }
+}
+
+template <typename T, int TX, int N1, typename Tout>
+__global__ __launch_bounds__(NT, 2) void k_fft4_inv(const T* __restrict__ spec, Tout* __restrict__ z,
+                                                    const double* __restrict__ invgam,
+                                                    const typename V2<T>::t* __restrict__ tw, int Nt,
+                                                    int S, int sx, int sy, int accumulate, int reverse,
+                                                    int tw_lds) {
+  using C = typename V2<T>::t;
+  using O2 = typename Out2<Tout>::t;
+  constexpr int NCOL = TX / 2, TPC = NT / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
+  constexpr int LDC = TPC + 1;
+  constexpr int KU = N1 / 2 + 1;         // spectrum rows k = r + TPC u < F
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
+  const int cstr = N1 * LDC + 1;
+  const int F = (Nt >> 1) + 1, half = Nt >> 1;
+  C* smtw = sm + NCOL * cstr;
+  const C* twp = tw_lds ? smtw : tw;
+  const int b = blockIdx.y, s0 = blockIdx.x * TX;
+  const T* specb = spec + (int64_t)b * F * sy * 2 * sx;
+  const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
+  const int s = s0 + 2 * j;
+  const bool vin = (sx & 1) == 0;
+  C a[KU], bb[KU];
+  {
+    const int y = s / sx, xx = s - y * sx;
+    const int y1 = (s + 1) / sx, xx1 = (s + 1) - y1 * sx;
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = r + TPC * u;
+      a[u] = C{0, 0};
+      bb[u] = C{0, 0};
+      if (k < F && s < S) {
+        const T* src = specb + ((int64_t)k * sy + y) * 2 * sx + xx;
+        if (vin && s + 1 < S) {
+          const C re = *reinterpret_cast<const C*>(src), im = *reinterpret_cast<const C*>(src + sx);
+          a[u] = C{re.x, im.x};
+          bb[u] = C{re.y, im.y};
+        } else {
+          a[u] = C{src[0], src[sx]};
+          if (s + 1 < S) {
+            const T* s1 = specb + ((int64_t)k * sy + y1) * 2 * sx + xx1;
+            bb[u] = C{s1[0], s1[sx]};
+          }
+        }
+      }
+    }
+  }
+  if (tw_lds) stage_twiddles(smtw, tw, Nt);
+  // 1. conj Z on the full circle in natural order (column j at j cstr)
+  C* colj = sm + j * cstr;
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    const int k = r + TPC * u;
+    if (k < F) {
+      const C A = a[u], Bv = bb[u];
+      if (k == 0 || k == half) {
+        colj[k] = C{A.x, -Bv.x};
+      } else {
+        colj[k] = C{A.x - Bv.y, -(A.y + Bv.x)};
+        colj[Nt - k] = C{A.x + Bv.y, A.y - Bv.x};
+      }
+    }
+  }
+  __syncthreads();
+  // 2. pencils, pass 1 in registers, sub-columns, TPC-point passes
+  C c[N1];
+#pragma unroll
+  for (int u = 0; u < N1; ++u) c[u] = colj[r + TPC * u];
+  __syncthreads();
+  fourstep_pass1<T, N1, TPC>(c, sm, twp, Nt, j, r, LDC, cstr);
+  __syncthreads();
+  fft_columns<T, N1>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
+  // 3. z = conj(fft(conj Z)) / Nt with Gamma^{-1}; sample n at (j, n mod N1) position n / N1
+  if (s >= S) return;
+  Tout* zb = z + (int64_t)b * Nt * S;
+  const bool vec = (S & 1) == 0 && s + 1 < S;
+  for (int n = r; n < Nt; n += TPC) {
+    const C yv = colj[(n & (N1 - 1)) * LDC + (n >> LOGN1)];
+    const double ig = invgam[n];
+    const double v0 = (double)yv.x * ig, v1 = -(double)yv.y * ig;
+    const int nd = reverse ? (Nt - 1 - n) : n;
+    Tout* dst = zb + (int64_t)nd * S + s;
+    if (vec) {
+      O2* d2 = reinterpret_cast<O2*>(dst);
+      if (accumulate) {
+        const O2 o = *d2;
+        *d2 = O2{(Tout)((double)o.x + v0), (Tout)((double)o.y + v1)};
+      } else {
+        *d2 = O2{(Tout)v0, (Tout)v1};
+      }
+    } else {
+      if (accumulate) dst[0] = (Tout)((double)dst[0] + v0);
+      else dst[0] = (Tout)v0;
+      if (s + 1 < S) {
+        if (accumulate) dst[1] = (Tout)((double)dst[1] + v1);
+        else dst[1] = (Tout)v1;
+      }
+    }
+  }
+}
+
+// LDS bytes of the four-step kernels' columns (stride N1 (TPC + 1) + 1);
+// the twiddle and Gamma tables follow when they fit.
+inline size_t fourstep_cols(int tx, int nt, size_t csize) {
+  const int ncol = tx / 2, tpc = NT / ncol, n1 = nt / tpc;
+  return (size_t)ncol * ((size_t)n1 * (tpc + 1) + 1) * csize;
+}
+
+// n1 > 0: four-step kernels; lds_inv: bytes of the inverse (no Gamma table)
+struct FftShape { int TX; size_t lds; bool gam_lds; int n1; bool tw_lds; size_t lds_inv; };
 
 // Widest tile (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex
 // columns of Nt+1 entries plus the twiddle table -- lets two workgroups share
@@ -347,9 +599,32 @@ FftShape choose_shape(const Plan& pl) {
   auto lds = [&](int tx) { return (size_t)(tx / 2) * (g.nt + 1) * csize + (size_t)g.nt * csize; };
   while (TX > 2 && (lds(TX) > budget || (int64_t)(TX / 2) * g.nt > (int64_t)ept * NT)) TX >>= 1;
   while (TX > 2 && TX / 2 >= g.S) TX >>= 1;  // no wider than the spatial extent needs
-  const size_t with_gam = lds(TX) + (size_t)g.nt * sizeof(double);
+  // four-step form when the pencil length N1 = Nt / TPC is 4 .. EPT and the
+  // tile is one of the instantiated widths
+  // (the twiddle table in LDS only when it fits beside the columns, else it
+  // is read through the caches)
+  // Preference: a tile of 16 or 32 columns (rows of 128 B or more) that
+  // lets three workgroups share a CU (measured faster at cfg2's shape),
+  // else the widest valid tile at two per CU.
+  const size_t twb = (size_t)g.nt * csize, gb = (size_t)g.nt * sizeof(double);
+  const size_t budget3 = 53 * 1024;
+  for (int pass = 0; pass < 2; ++pass) {
+    const size_t lim = pass == 0 ? budget3 : budget;
+    for (int tx4 = 32; tx4 >= (pass == 0 ? 16 : 8); tx4 >>= 1) {
+      const int ncol = tx4 / 2, tpc = NT / ncol, n1 = g.nt / tpc;
+      if (tx4 / 2 >= g.S && tx4 > 8) continue;
+      if (n1 < 4 || n1 > ept || n1 * tpc != g.nt) continue;
+      const size_t cols = fourstep_cols(tx4, g.nt, csize);
+      if (cols > lim) continue;
+      const bool twl = cols + twb <= lim;
+      const size_t inv = cols + (twl ? twb : 0);
+      const bool gl = inv + gb <= lim;
+      return FftShape{tx4, inv + (gl ? gb : 0), gl, n1, twl, inv};
+    }
+  }
+  const size_t with_gam = lds(TX) + gb;
   const bool gam_lds = with_gam <= budget;
-  return FftShape{TX, gam_lds ? with_gam : lds(TX), gam_lds};
+  return FftShape{TX, gam_lds ? with_gam : lds(TX), gam_lds, 0, true, lds(TX)};
 }
 
 template <typename T>
@@ -360,6 +635,23 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
   int logNt = 0;
   while ((1 << logNt) < g.nt) ++logNt;
   dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
+  if (sh.n1 > 0) {
+#define PD_FWD4(W, N)                                                                      \
+  if (sh.TX == W && sh.n1 == N) {                                                          \
+    hipFuncSetAttribute((const void*)k_fft4_fwd<T, W, N>,                                  \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
+    k_fft4_fwd<T, W, N><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt,      \
+                                                 (int)g.S, g.sx, g.sy, reverse, sh.gam_lds, \
+                                                 sh.tw_lds);                               \
+    return;                                                                                \
+  }
+    PD_FWD4(8, 4) PD_FWD4(8, 8) PD_FWD4(8, 16) PD_FWD4(16, 4) PD_FWD4(16, 8) PD_FWD4(16, 16)
+    PD_FWD4(32, 4) PD_FWD4(32, 8) PD_FWD4(32, 16)
+    if constexpr (FftTraits<T>::EPT >= 32) {
+      PD_FWD4(8, 32) PD_FWD4(16, 32) PD_FWD4(32, 32)
+    }
+#undef PD_FWD4
+  }
 #define PD_FWD(W)                                                                          \
   case W:                                                                                  \
     hipFuncSetAttribute((const void*)k_fft_fwd<T, W>,                                      \
@@ -382,6 +674,24 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
   int logNt = 0;
   while ((1 << logNt) < g.nt) ++logNt;
   dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
+  if (sh.n1 > 0) {
+    const size_t lds4 = sh.lds_inv;
+#define PD_INV4(W, N)                                                                      \
+  if (sh.TX == W && sh.n1 == N) {                                                          \
+    hipFuncSetAttribute((const void*)k_fft4_inv<T, W, N, Tout>,                            \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);            \
+    k_fft4_inv<T, W, N, Tout><<<grid, NT, lds4, s>>>(spec, z, pl.d_invgam, tw, g.nt,       \
+                                                     (int)g.S, g.sx, g.sy, accumulate,     \
+                                                     reverse, sh.tw_lds);                  \
+    return;                                                                                \
+  }
+    PD_INV4(8, 4) PD_INV4(8, 8) PD_INV4(8, 16) PD_INV4(16, 4) PD_INV4(16, 8) PD_INV4(16, 16)
+    PD_INV4(32, 4) PD_INV4(32, 8) PD_INV4(32, 16)
+    if constexpr (FftTraits<T>::EPT >= 32) {
+      PD_INV4(8, 32) PD_INV4(16, 32) PD_INV4(32, 32)
+    }
+#undef PD_INV4
+  }
 #define PD_INV(W)                                                                          \
   case W:                                                                                  \
     hipFuncSetAttribute((const void*)k_fft_inv<T, W, Tout>,                                \

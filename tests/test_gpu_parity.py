@@ -85,6 +85,38 @@ def test_schur_sweep_shapes(nx, ny, prec):
     assert err < PREC_TOL[prec]
 
 
+# Time-FFT shapes: on a 16 x 8 grid (sine basis) these Nt select the
+# four-step kernels with pencil lengths 4 .. 32 and tiles of 32, 16 and 8
+# columns (Nt = 2048 reads its twiddles through the caches), and the
+# Stockham kernel below them.
+FFT_NT = {"fp32": [16, 64, 128, 256, 512, 2048], "fp64": [16, 64, 256, 512, 1024]}
+
+
+@pytest.mark.parametrize("prec,nt", [(p, n) for p, ns in FFT_NT.items() for n in ns])
+def test_time_fft_shapes(prec, nt):
+    announce(f"fft shape nt={nt} {prec}")
+    cfg = dict(dim=2, nx=16, ny=8, nt=nt, scheme="tr", T=1.0, nu=0.05, alpha=1e-2)
+    torch, pd, prob = make(cfg, prec)
+    r = np.random.default_rng(11).standard_normal((prob.nt, prob.nspace))
+    z_ref = o_prec.three_steps(prob, r)
+    z = pd.apply_precond(to_gpu(torch, r, pd.shape))
+    torch.cuda.synchronize()
+    err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
+    print(f"  rel err {err:.3e}")
+    assert err < PREC_TOL[prec]
+
+
+def test_adjoint_solve_long_time():
+    announce("adjoint nt=256 (time-reversed four-step transforms)")
+    cfg = dict(dim=2, nx=16, ny=8, nt=256, scheme="be", T=1.0, nu=0.05, ax=0.5, ay=0.3, alpha=1e-2)
+    torch, pd, prob = make(cfg, "fp64")
+    g = np.random.default_rng(12).standard_normal((prob.nt, prob.nspace))
+    lam, res = pd.adjoint_solve(to_gpu(torch, g, pd.shape), rtol=1e-12, max_iter=60)
+    assert res.converged
+    ref = o_adj.sequential_transpose(prob, g)
+    assert rel_err(lam.cpu().numpy().reshape(prob.nt, -1), ref) < 1e-10
+
+
 @pytest.mark.parametrize("case", ["1d-be", "2d-tr-schur", "2d-lf-dst", "2d-be-schur-ragged"])
 def test_precond_in_place_and_batch(case):
     announce(f"precond batch/in-place {case}")
