@@ -273,20 +273,67 @@ __device__ __forceinline__ void coupling_lds(const T* sre, const T* sim, const T
   }
 }
 
+// One wave copies rows [y0, y1) of a full tile of NB modes (k0 .. k0+NB-1)
+// into LDS: 16-byte vectors of consecutive modes when VEC (sx % 4 == 0), all
+// loads issued before the LDS stores.  MAXR bounds y1 - y0.
+template <typename T, int NB, int MAXR, bool VEC>
+__device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, int k0, int sx, int y0,
+                                               int y1, int ldy, int R, int lane) {
+  if constexpr (VEC) {
+    using V = typename Vec16<T>::t;
+    constexpr int MV = Vec16<T>::n, NV = NB / MV;
+    constexpr int MAXU = (MAXR * 2 * NV + 63) / 64;
+    const int total = (y1 - y0) * 2 * NV;
+    V v[MAXU];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+      const int e = lane + 64 * u;
+      if (e < total) {
+        const int kv = e % NV, comp = (e / NV) & 1, y = y0 + e / (2 * NV);
+        v[u] = *reinterpret_cast<const V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+      const int e = lane + 64 * u;
+      if (e < total) {
+        const int kv = e % NV, comp = (e / NV) & 1, y = y0 + e / (2 * NV);
+        T* dst = comp ? sim : sre;
+#pragma unroll
+        for (int m = 0; m < MV; ++m) dst[lidx(kv * MV + m, y, ldy, R)] = vget<T>(v[u], m);
+      }
+    }
+  } else {
+    const int total = (y1 - y0) * 2 * NB;
+    for (int e = lane; e < total; e += 64) {
+      const int k = e % NB, comp = (e / NB) & 1, y = y0 + e / (2 * NB);
+      (comp ? sim : sre)[lidx(k, y, ldy, R)] = slice[(int64_t)y * 2 * sx + comp * sx + k0 + k];
+    }
+  }
+}
+
 // Pipelined back-sweep: one workgroup of 1 + NCW waves per (right-hand side,
-// frequency) slice.  While wave 0 solves block b of NB modes (lines held in
-// registers, right-looking updates inside the block, DPP scans), waves 1..NCW
-// stage the tile of block b-1 and compute its coupling to every mode solved
-// before b on MFMA (RB 16-row blocks each); after the barrier they add the
-// coupling to block b itself from the LDS tile and subtract lambda2 times the
-// total.  Tiles and the in-block coupling coefficients lambda2 T are
-// double-buffered in LDS.  One wave per SIMD, so each wave has the whole
-// register file (wave 0 keeps NB x R complex values per lane).
+// frequency) slice; blocks of NB modes from the last to the first.  Step b:
+//   * all waves write block b+1 (solved in the previous step) from LDS to
+//     global memory; barrier;
+//   * wave 0 takes block b's tile (already carrying its coupling to every
+//     mode beyond block b+1), subtracts the coupling to block b+1 from the
+//     solution of b+1 it still holds in registers, and solves the NB lines in
+//     order (DPP scans, right-looking updates inside the block); the near
+//     coupling of a line is independent of the scans before it, so the
+//     compiler interleaves the two;
+//   * meanwhile waves 1..NCW stage block b-1's tile and subtract lambda2 times
+//     its coupling to all modes beyond block b (MFMA products on fragments
+//     read from global memory, one 16-mode step prefetched), and stage the
+//     coefficients block b-1 needs: lambda2 T inside it and towards block b;
+//   * barrier.
+// Tiles and coefficient blocks are double-buffered in LDS.  One wave per SIMD
+// per workgroup; with NB = 8 two workgroups share a CU.
 constexpr int NCW = 3;
 constexpr int SWT = 64 * (NCW + 1);
 
-template <typename T, int R, int P, int NB, int RB, bool VEC>
-__global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
+template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB>
+__global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                      const T* __restrict__ tup, const T* __restrict__ lu,
                                                      double lo, double up, int F, int sx, int sy, int ldy) {
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
@@ -295,7 +342,11 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
   extern __shared__ __align__(16) unsigned char smraw[];
   T* tiles = reinterpret_cast<T*>(smraw);       // [2 buffers][re, im][NB][ldy]
   const int TS = 2 * NB * ldy;
-  T* tbs = tiles + 2 * TS;                      // [2 buffers][re, im][NB][NB]: lambda2 T_{q' q}, q' < q
+  T* tbs = tiles + 2 * TS;                      // [2][NB][NB] complex: lambda2 T_{q' q} inside the block, q' < q
+  T* tns = tbs + 4 * NB * NB;                   // [2][NB][NB] complex: lambda2 T_{q j} towards the block after
+  // wave 0's copy of the block it solved last: value i of line q of lane l at
+  // (q R + i) 64 + l (conflict-free), read back by the next step's near coupling
+  Cx<T>* wsol = reinterpret_cast<Cx<T>*>(tns + 4 * NB * NB);
 
   const int n = blockIdx.x, b = blockIdx.y;
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
@@ -306,24 +357,25 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
   const int wave = threadIdx.x >> 6;
   const int nblk = (sx + NB - 1) / NB;
 
-  auto stage_tb = [&](int buf, int k0, int nk, int t, int nthr) {
-    T* bt = tbs + buf * 2 * NB * NB;   // (re, im) pairs
+  // lambda2 T[k0a + qa][k0b + qb] for qa, qb < NB (zero outside the valid
+  // range: qb >= nkb, or qa >= qb when the two blocks coincide)
+  auto stage_coef = [&](T* dst, int k0a, int k0b, int nkb, bool upper, int t, int nthr) {
     for (int e = t; e < NB * NB; e += nthr) {
       const int qa = e / NB, qb = e - qa * NB;
       T tr = 0, ti = 0;
-      if (qa < qb && qb < nk) {
-        tr = tre[(int64_t)(k0 + qa) * sx + k0 + qb];
-        ti = tim[(int64_t)(k0 + qa) * sx + k0 + qb];
+      if (qb < nkb && (!upper || qa < qb)) {
+        tr = tre[(int64_t)(k0a + qa) * sx + k0b + qb];
+        ti = tim[(int64_t)(k0a + qa) * sx + k0b + qb];
       }
-      bt[2 * e] = l2r * tr - l2i * ti;
-      bt[2 * e + 1] = l2r * ti + l2i * tr;
+      dst[2 * e] = l2r * tr - l2i * ti;
+      dst[2 * e + 1] = l2r * ti + l2i * tr;
     }
   };
 
   {  // prologue: the last block (the only one that may be partial)
     const int k0 = (nblk - 1) * NB, nk = sx - k0;
     tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
-    stage_tb(0, k0, nk, (int)threadIdx.x, SWT);
+    stage_coef(tbs, k0, k0, nk, true, (int)threadIdx.x, SWT);
   }
   __syncthreads();
 
@@ -340,16 +392,21 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
     T* cim = cre + NB * ldy;
     T* nre = tiles + nxt * TS;
     T* nim = nre + NB * ldy;
+    if (st > 0) {   // block kb+1, solved in the previous step, to global memory
+      const int k0p = k0 + NB, nkp = min(NB, sx - k0p);
+      if (VEC && nkp == NB) tile_store_vec<T, NB, R * P>(slice, nre, nim, k0p, sx, sy, ldy, R, tid, SWT);
+      else tile_store_by(slice, nre, nim, k0p, nkp, NB, sx, sy, ldy, R, tid, SWT);
+    }
+    __syncthreads();   // block kb+1 in global memory; its LDS buffer is free
     const int k0n = k0 - NB;   // next block (always full) when kb > 0
-    typename MF::acc_t acc[RB][NCB];
-    T tn_r[4], tn_i[4];        // T entries of the near coupling
     if (wave == 0) {
-      // ---- sequential solve of block kb -------------------------------
+      // ---- block kb: near coupling, then its lines in order ------------
       const bool active = lane < P;
       const int p = lane % P;
       const Cx<T> ca = active ? Cx<T>{(T)(l2.x * lo), (T)(l2.y * lo)} : cz<T>();
       const Cx<T> cc = active ? Cx<T>{(T)(l2.x * up), (T)(l2.y * up)} : cz<T>();
       const Cx<T>* tbc = reinterpret_cast<const Cx<T>*>(tbs + cur * 2 * NB * NB);
+      const Cx<T>* tnc = reinterpret_cast<const Cx<T>*>(tns + cur * 2 * NB * NB);
       const T* lun = lu + (int64_t)n * sx * sy * 2;
       auto load_inv = [&](int q, Cx<T> (&iv)[R]) {
         const T* src = lun + ((int64_t)(k0 + q) * sy + p * R) * 2;
@@ -370,41 +427,72 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
 #pragma unroll
       for (int q = NB - 1; q >= 0; --q) {
         if (q < nk) {
+          // coupling to block kb+1 (zero coefficients in the first step)
+          if (st > 0) {
+#pragma unroll
+            for (int jq = 0; jq < NB; ++jq) {
+              const Cx<T> t = tnc[q * NB + jq];
+#pragma unroll
+              for (int i = 0; i < R; ++i) {
+                const Cx<T> x = wsol[(jq * R + i) * 64 + lane];
+                d[q][i].x = fma(-t.x, x.x, fma(t.y, x.y, d[q][i].x));
+                d[q][i].y = fma(-t.x, x.y, fma(-t.y, x.x, d[q][i].y));
+              }
+            }
+          }
           Cx<T> iv[R];
 #pragma unroll
           for (int i = 0; i < R; ++i) iv[i] = ivn[i];
           if (q > 0) load_inv(q - 1, ivn);
           lu_scan_dpp<T, R, P>(d[q], iv, ca, cc, sy, lane);
+          // d_qa -= t w_q inside the block, four fused multiply-adds per value
 #pragma unroll
           for (int qa = 0; qa < q; ++qa) {
-            // d_qa -= t w_q, in four fused multiply-adds per complex value
             const Cx<T> t = tbc[qa * NB + q];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-              const Cx<T> w = d[q][i];
-              d[qa][i].x = fma(-t.x, w.x, fma(t.y, w.y, d[qa][i].x));
-              d[qa][i].y = fma(-t.x, w.y, fma(-t.y, w.x, d[qa][i].y));
+              const Cx<T> x = d[q][i];
+              d[qa][i].x = fma(-t.x, x.x, fma(t.y, x.y, d[qa][i].x));
+              d[qa][i].y = fma(-t.x, x.y, fma(-t.y, x.x, d[qa][i].y));
             }
           }
         }
       }
-      if (active) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const int idx = q * ldy + p * (R + 1) + i;
-            if (q < nk) {
-              cre[idx] = d[q][i].x;
-              cim[idx] = d[q][i].y;
-            }
+        for (int i = 0; i < R; ++i) {
+          wsol[(q * R + i) * 64 + lane] = (q < nk) ? d[q][i] : cz<T>();
+          const int idx = q * ldy + p * (R + 1) + i;
+          if (active && q < nk) {
+            cre[idx] = d[q][i].x;
+            cim[idx] = d[q][i].y;
           }
-      }
+        }
     } else if (kb > 0) {
-      // ---- next block: stage its tile, coupling to the modes >= kend -----
+      // ---- block kb-1: tile, coupling to the modes beyond block kb -----
+      // Wave cw stages exactly the rows its accumulators cover, so its
+      // subtraction depends only on its own LDS writes (in program order).
       const int ct = tid - 64, cw = wave - 1;
-      if (VEC) tile_load_vec<T, NB, R * P, SWT - 64>(slice, nre, nim, k0n, sx, sy, ldy, R, ct, SWT - 64);
-      else tile_load_by(slice, nre, nim, k0n, NB, NB, sx, sy, ldy, R, ct, SWT - 64);
+      const int y0 = cw * RB * 16, y1 = min(sy, y0 + RB * 16);
+      // coefficients of block kb-1 (inside it; towards block kb): loads
+      // issued now, their latency hidden behind the tile and the products
+      static_assert(NB * NB <= SWT - 64, "one coefficient per thread");
+      T cbr = 0, cbi = 0, cnr = 0, cni = 0;
+      if (ct < NB * NB) {
+        const int qa = ct / NB, qb = ct - qa * NB;
+        const int64_t row = (int64_t)(k0n + qa) * sx;
+        if (qa < qb) {
+          cbr = tre[row + k0n + qb];
+          cbi = tim[row + k0n + qb];
+        }
+        if (qb < nk) {
+          cnr = tre[row + k0 + qb];
+          cni = tim[row + k0 + qb];
+        }
+      }
+      tile_rows_load<T, NB, RB * 16, VEC>(slice, nre, nim, k0n, sx, y0, y1, ldy, R, lane);
+      typename MF::acc_t acc[RB][NCB];
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -412,38 +500,53 @@ __global__ __launch_bounds__(SWT, 1) void k_schur_sweep(T* __restrict__ spec, co
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
       coupling_far<T, NB, RB, VEC>(slice, tre, tim, sx, sy, k0n, kend, cw, lr, lk, acc);
-      // ahead of the barrier: the next block's in-block coefficients and the
-      // T entries of its coupling to the block being solved
-      stage_tb(nxt, k0n, NB, ct, SWT - 64);
-      near_t<T, NB>(tn_r, tn_i, tre, tim, sx, k0n, k0, nk, lr, lk);
-    }
-    __syncthreads();   // block kb solved in LDS; next tile staged
-    if (wave != 0 && kb > 0) {
-      const int cw = wave - 1;
-      coupling_lds<T, NB, RB, R>(cre, cim, tn_r, tn_i, sy, ldy, nk, cw, lr, lk, acc);
+      // tile -= lambda2 C: all LDS reads first, then all writes (one
+      // read-modify-write at a time would expose the LDS latency per value)
+      const bool col_ok = NCB == 2 || lr < 8;
+      T tr_[RB][4], ti_[RB][4];
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int y = cw * RB * 16 + i * 16 + MF::row(lk, v);
+          const int y = y0 + i * 16 + MF::row(lk, v);
+          const int idx = lidx(lr, y, ldy, R);
+          tr_[i][v] = (y < sy && col_ok) ? nre[idx] : (T)0;
+          ti_[i][v] = (y < sy && col_ok) ? nim[idx] : (T)0;
+        }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = y0 + i * 16 + MF::row(lk, v);
           T cr, ci;
           if constexpr (NCB == 2) {
             cr = acc[i][0][v];
             ci = acc[i][1][v];
           } else {
             cr = acc[i][0][v];
-            ci = __shfl_down(acc[i][0][v], 8, 16);   // imaginary part from lane lr + 8
+            ci = dpp_mov<0x108>(acc[i][0][v]);   // imaginary part from lane lr + 8 (row_shl:8)
           }
-          if (y < sy && (NCB == 2 || lr < 8)) {
+          if (y < sy && col_ok) {
             const int idx = lidx(lr, y, ldy, R);
-            nre[idx] -= l2r * cr - l2i * ci;
-            nim[idx] -= l2r * ci + l2i * cr;
+            nre[idx] = tr_[i][v] - (l2r * cr - l2i * ci);
+            nim[idx] = ti_[i][v] - (l2r * ci + l2i * cr);
           }
         }
+      if (ct < NB * NB) {
+        T* bt = tbs + nxt * 2 * NB * NB;
+        T* bn = tns + nxt * 2 * NB * NB;
+        bt[2 * ct] = l2r * cbr - l2i * cbi;
+        bt[2 * ct + 1] = l2r * cbi + l2i * cbr;
+        bn[2 * ct] = l2r * cnr - l2i * cni;
+        bn[2 * ct + 1] = l2r * cni + l2i * cnr;
+      }
     }
-    if (VEC && nk == NB) tile_store_vec<T, NB, R * P>(slice, cre, cim, k0, sx, sy, ldy, R, tid, SWT);
-    else tile_store_by(slice, cre, cim, k0, nk, NB, sx, sy, ldy, R, tid, SWT);
-    __syncthreads();   // block kb in global memory; next tile and its T block ready
+    __syncthreads();   // block kb solved (LDS buffer cur); block kb-1 staged
+  }
+  {  // the first block, solved in the last step
+    const int nkp = min(NB, sx);
+    T* pre = tiles + ((nblk - 1) & 1) * TS;
+    tile_store_by(slice, pre, pre + NB * ldy, 0, nkp, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
   }
 }
 
@@ -726,7 +829,8 @@ void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
 // Pipelined kernel: LDS bytes of two tiles and two coupling blocks.
 template <typename T, int NB>
 size_t piped_lds(const SweepShape& sh) {
-  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)4 * NB * NB);
+  // two tiles, two pairs of coefficient blocks, wave 0's solution copy
+  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64);
 }
 
 template <typename T, int R, int P, int NB, int RB>
@@ -734,7 +838,11 @@ void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, 16>(pl);
   const size_t lds = piped_lds<T, NB>(sh);
-  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true> : k_schur_sweep<T, R, P, NB, RB, false>;
+  // two workgroups per CU where the registers allow (lines of up to 256 rows):
+  // an odd number of slices, or more slices than CUs, then leaves no CU idle
+  // while a last slice runs alone
+  constexpr int MINB = (R == 4) ? 2 : 1;
+  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB> : k_schur_sweep<T, R, P, NB, RB, false, MINB>;
   hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
                                        g.F, g.sx, g.sy, sh.ldy);
@@ -746,9 +854,10 @@ template <> struct SweepCfg<float> { static constexpr int NB = 16, BK = 32, NB8 
 template <> struct SweepCfg<double> { static constexpr int NB = 8, BK = 16, NB8 = 8, BK8 = 16; };
 
 // Modes per block of the pipelined kernel: the block's lines live in wave 0's
-// registers (NB x R complex values per lane).
+// registers (NB x R complex values per lane); 8 keeps the kernel within two
+// workgroups per CU (42 KiB of LDS at 256 rows).
 template <typename T> struct PipedCfg;
-template <> struct PipedCfg<float> { static constexpr int NB4 = 16, NB8 = 8; };
+template <> struct PipedCfg<float> { static constexpr int NB4 = 8, NB8 = 8; };
 template <> struct PipedCfg<double> { static constexpr int NB4 = 0, NB8 = 0; };
 
 // float64 keeps the one-phase kernel: its coupling product (half the float32
