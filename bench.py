@@ -181,6 +181,22 @@ def roofline(run, cfg, traffic_file):
             "algorithmic_flops_per_launch": fl / max(cnt, 1)}
 
 
+def stage_rooflines(run):
+    """Per-stage average launch time and achieved rate against the stage's bound."""
+    out = {}
+    for name, (ms, cnt, by, fl) in run["stages"].items():
+        if cnt == 0:
+            continue
+        avg_s = ms / 1e3 / cnt
+        rec = {"launches": cnt, "avg_launch_ms": round(ms / cnt, 5),
+               "GBs": round(by / cnt / avg_s / 1e9, 1),
+               "hbm_frac": round(by / cnt / avg_s / 1e9 / PEAK["hbm_GBs"], 4)}
+        if fl:
+            rec["TFs"] = round(fl / cnt / avg_s / 1e12, 2)
+        out[name] = rec
+    return out
+
+
 def cpu_baseline(cfg):
     """The oracle's sequential float64 time stepper on one right-hand side (host, 1 thread)."""
     from threadpoolctl import threadpool_limits
@@ -267,6 +283,7 @@ def main():
         "stage_ms_per_step_fp64": None if fp64 is None else
         {k: round(v[0] / args.steps, 4) for k, v in fp64["stages"].items()},
         "roofline": roofline(mixed, cfg, args.traffic),
+        "stage_roofline": stage_rooflines(mixed),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)

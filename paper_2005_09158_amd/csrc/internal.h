@@ -16,8 +16,28 @@ using cd = std::complex<double>;
 
 bool complex_schur(int n, std::vector<cd>& h, std::vector<cd>& q);
 
+// Workgroup order for the chip's 8 XCDs.  The dispatcher deals consecutive
+// workgroup ids round-robin to the XCDs, each with its own L2; renumbering
+// id -> (id mod 8) * share + id / 8 hands every XCD one contiguous range of
+// tiles, so workgroups that read or write neighbouring pieces of the same
+// cache lines (adjacent columns of a row, the rows of a stencil) share an L2
+// while they run.  A bijection of [0, total) for every total.
+__device__ __forceinline__ unsigned xcd_order(unsigned id, unsigned total) {
+  const unsigned q = total >> 3, rem = total & 7, x = id & 7, i = id >> 3;
+  return x < rem ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+}
+
+// This workgroup's (x, y, z) grid position after xcd_order.
+struct BlockPos { int x, y, z; };
+__device__ __forceinline__ BlockPos xcd_block() {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned id = xcd_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  return BlockPos{(int)(id % gx), (int)((id / gx) % gy), (int)(id / (gx * gy))};
+}
+
 // Numeric formats of the preconditioner.
-// BF16: split hi+lo product (3 bf16 MFMAs); BF16X1: single bf16 product.
+// BF16: operands split into three bf16 parts (six bf16 MFMAs per product);
+// BF16X1: single bf16 product.
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X1 = 3 };
 
 // Geometry of the spectral buffer [batch][F][sy][2][sx]: F = nt/2 + 1

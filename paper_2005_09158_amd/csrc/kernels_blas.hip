@@ -27,52 +27,110 @@ struct Stencil {
 template <typename Tin>
 __device__ __forceinline__ double ld(const Tin* p) { return (double)*p; }
 
+// V consecutive values from p (16-byte aligned when V > 1) as doubles.
+template <typename Tin, int V>
+__device__ __forceinline__ void ldv(const Tin* p, double (&o)[V]) {
+  if constexpr (V == 1) {
+    o[0] = (double)*p;
+  } else if constexpr (sizeof(Tin) == 4) {
+#pragma unroll
+    for (int h = 0; h < V; h += 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p + h);
+      o[h] = q.x; o[h + 1] = q.y; o[h + 2] = q.z; o[h + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < V; h += 2) {
+      const double2 q = *reinterpret_cast<const double2*>(p + h);
+      o[h] = q.x; o[h + 1] = q.y;
+    }
+  }
+}
+
+// u and K u at the V points x .. x+V-1 of row y (x % V == 0, nx % V == 0).
+// Each point's stencil terms are added in the order centre, x-1, x+1, y-1, y+1.
+template <typename Tin, int V>
+__device__ __forceinline__ void points_and_k(const Tin* un, int x, int y, int nx, int ny,
+                                             const Stencil& st, double (&u)[V], double (&ku)[V]) {
+  const Tin* c = un + (int64_t)y * nx + x;
+  double up[V], dn[V];
+  ldv<Tin, V>(c, u);
+  if (y > 0) ldv<Tin, V>(c - nx, up);
+  if (y < ny - 1) ldv<Tin, V>(c + nx, dn);
+  const double lft = x > 0 ? ld(c - 1) : 0.0, rgt = x + V < nx ? ld(c + V) : 0.0;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double k = st.d * u[v];
+    if (x + v > 0) k += st.xl * (v ? u[v - 1] : lft);
+    if (x + v < nx - 1) k += st.xu * (v + 1 < V ? u[v + 1] : rgt);
+    if (y > 0) k += st.yl * up[v];
+    if (y < ny - 1) k += st.yu * dn[v];
+    ku[v] = k;
+  }
+}
+
 template <typename Tin>
 __device__ __forceinline__ void point_and_k(const Tin* un, int x, int y, int nx, int ny,
                                             const Stencil& st, double& u, double& ku) {
-  const Tin* c = un + (int64_t)y * nx + x;
-  u = ld(c);
-  double k = st.d * u;
-  if (x > 0) k += st.xl * ld(c - 1);
-  if (x < nx - 1) k += st.xu * ld(c + 1);
-  if (y > 0) k += st.yl * ld(c - nx);
-  if (y < ny - 1) k += st.yu * ld(c + nx);
-  ku = k;
+  double uu[1], kk[1];
+  points_and_k<Tin, 1>(un, x, y, nx, ny, st, uu, kk);
+  u = uu[0];
+  ku = kk[0];
 }
 
-// dir = +1: y = A u ;  dir = -1: y = A^T u (stencil already transposed by the caller).
-template <typename Tin>
+// dir = +1: y = A u ;  dir = -1: y = A^T u (stencil already transposed by the
+// caller).  V = 4: four consecutive points per thread with 16-byte row loads
+// (nx % 4 == 0), which keeps four times the bytes in flight per load.
+template <typename Tin, int V>
 __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const double* __restrict__ b,
                                                double* __restrict__ yv, int Nt, int nx, int ny, int L,
                                                double c10, double c11, double c12, double c20,
                                                double c21, double c22, Stencil st, int chunk, int dir) {
   const int S = nx * ny;
-  const int s = blockIdx.x * NT + threadIdx.x;
+  const BlockPos bp = xcd_block();   // neighbouring rows of the stencil on one L2
+  const int s = (bp.x * NT + threadIdx.x) * V;
   if (s >= S) return;
   const int x = s % nx, y = s / nx;
-  const int64_t boff = (int64_t)blockIdx.z * Nt * S;
+  const int64_t boff = (int64_t)bp.z * Nt * S;
   const Tin* ub = u + boff;
   double* yb = yv + boff;
   const double* bb = b ? b + boff : nullptr;
-  const int nbeg = blockIdx.y * chunk;
+  const int nbeg = bp.y * chunk;
   const int nend = min(Nt, nbeg + chunk);
-  double u1 = 0, k1 = 0, u2 = 0, k2 = 0;  // history: step -1 and -2 along the march
+  double u1[V], k1[V], u2[V], k2[V];  // history: step -1 and -2 along the march
+#pragma unroll
+  for (int v = 0; v < V; ++v) u1[v] = k1[v] = u2[v] = k2[v] = 0.0;
   // prologue: the L-1 steps preceding the chunk in marching order
   for (int h = L - 1; h >= 1; --h) {
-    int m = (dir > 0) ? (nbeg - h) : (nend - 1 + h);
-    double uu = 0, kk = 0;
-    if (m >= 0 && m < Nt) point_and_k(ub + (int64_t)m * S, x, y, nx, ny, st, uu, kk);
-    u2 = u1; k2 = k1; u1 = uu; k1 = kk;
+    const int m = (dir > 0) ? (nbeg - h) : (nend - 1 + h);
+    double uu[V], kk[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) uu[v] = kk[v] = 0.0;
+    if (m >= 0 && m < Nt) points_and_k<Tin, V>(ub + (int64_t)m * S, x, y, nx, ny, st, uu, kk);
+#pragma unroll
+    for (int v = 0; v < V; ++v) { u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = uu[v]; k1[v] = kk[v]; }
   }
   for (int i = 0; i < nend - nbeg; ++i) {
-    int n = (dir > 0) ? (nbeg + i) : (nend - 1 - i);
-    double u0, k0;
-    point_and_k(ub + (int64_t)n * S, x, y, nx, ny, st, u0, k0);
-    double r = c10 * u0 + c20 * k0 + c11 * u1 + c21 * k1;
-    if (L > 2) r += c12 * u2 + c22 * k2;
-    int64_t off = (int64_t)n * S + s;
-    yb[off] = bb ? (bb[off] - r) : r;
-    u2 = u1; k2 = k1; u1 = u0; k1 = k0;
+    const int n = (dir > 0) ? (nbeg + i) : (nend - 1 - i);
+    double u0[V], k0[V];
+    points_and_k<Tin, V>(ub + (int64_t)n * S, x, y, nx, ny, st, u0, k0);
+    const int64_t off = (int64_t)n * S + s;
+    double bv[V];
+    if (bb) ldv<double, V>(bb + off, bv);
+    double r[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r[v] = c10 * u0[v] + c20 * k0[v] + c11 * u1[v] + c21 * k1[v];
+      if (L > 2) r[v] += c12 * u2[v] + c22 * k2[v];
+      if (bb) r[v] = bv[v] - r[v];
+      u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = u0[v]; k1[v] = k0[v];
+    }
+    if constexpr (V == 1) {
+      yb[off] = r[0];
+    } else {
+#pragma unroll
+      for (int h = 0; h < V; h += 2) *reinterpret_cast<double2*>(yb + off + h) = double2{r[h], r[h + 1]};
+    }
   }
 }
 
@@ -317,17 +375,22 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
             double* y, int transpose, hipStream_t s) {
   const Geom& g = pl.g;
   const int chunk = 16;
-  dim3 grid((g.S + NT - 1) / NT, (g.nt + chunk - 1) / chunk, g.B);
+  const int V = (g.nx % 4) == 0 ? 4 : 1;
+  dim3 grid((unsigned)((g.S / V + NT - 1) / NT), (g.nt + chunk - 1) / chunk, g.B);
   Stencil st = stencil_of(op);
   int dir = transpose ? -1 : 1;
-  if (u_is_f32)
-    k_matvec<float><<<grid, NT, 0, s>>>((const float*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0],
-                                        pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,
-                                        chunk, dir);
-  else
-    k_matvec<double><<<grid, NT, 0, s>>>((const double*)u, b, y, g.nt, g.nx, g.ny, pl.L,
-                                         pl.c1[0], pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1],
-                                         pl.c2[2], st, chunk, dir);
+#define PD_MV(TIN, VV)                                                                            \
+  k_matvec<TIN, VV><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0],    \
+                                        pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,     \
+                                        chunk, dir)
+  if (u_is_f32) {
+    if (V == 4) PD_MV(float, 4);
+    else PD_MV(float, 1);
+  } else {
+    if (V == 4) PD_MV(double, 4);
+    else PD_MV(double, 1);
+  }
+#undef PD_MV
 }
 
 void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,

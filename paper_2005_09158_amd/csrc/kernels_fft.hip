@@ -173,8 +173,9 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
   C* sm = reinterpret_cast<C*>(smraw);
   const int ld = Nt + 1, F = (Nt >> 1) + 1;
   C* smtw = sm + NCOL * ld;
-  const int b = blockIdx.y;
-  const int s0 = blockIdx.x * TX;
+  const BlockPos bp = xcd_block();
+  const int b = bp.y;
+  const int s0 = bp.x * TX;
   const double* xb = x + (int64_t)b * Nt * S;
   const double sc = bscale ? bscale[b] : 1.0;
   const bool vec = (S & 1) == 0;
@@ -259,8 +260,9 @@ __global__ __launch_bounds__(NT, 2) void k_fft_inv(const T* __restrict__ spec, T
   C* sm = reinterpret_cast<C*>(smraw);
   const int ld = Nt + 1, F = (Nt >> 1) + 1, half = Nt >> 1;
   C* smtw = sm + NCOL * ld;
-  const int b = blockIdx.y;
-  const int s0 = blockIdx.x * TX;
+  const BlockPos bp = xcd_block();
+  const int b = bp.y;
+  const int s0 = bp.x * TX;
   const T* specb = spec + (int64_t)b * F * sy * 2 * sx;
   stage_twiddles(smtw, tw, Nt);
   const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
@@ -417,7 +419,8 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x
   C* smtw = sm + NCOL * cstr;
   double* smg = reinterpret_cast<double*>(smtw + (tw_lds ? Nt : 0));
   const C* twp = tw_lds ? smtw : tw;     // twiddles in LDS, or through the caches
-  const int b = blockIdx.y, s0 = blockIdx.x * TX;
+  const BlockPos bp = xcd_block();
+  const int b = bp.y, s0 = bp.x * TX;
   const double* xb = x + (int64_t)b * Nt * S;
   const double sc = bscale ? bscale[b] : 1.0;
   const bool vec = (S & 1) == 0;
@@ -490,7 +493,8 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_inv(const T* __restrict__ spec, 
   const int F = (Nt >> 1) + 1, half = Nt >> 1;
   C* smtw = sm + NCOL * cstr;
   const C* twp = tw_lds ? smtw : tw;
-  const int b = blockIdx.y, s0 = blockIdx.x * TX;
+  const BlockPos bp = xcd_block();
+  const int b = bp.y, s0 = bp.x * TX;
   const T* specb = spec + (int64_t)b * F * sy * 2 * sx;
   const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
   const int s = s0 + 2 * j;
@@ -604,13 +608,14 @@ FftShape choose_shape(const Plan& pl) {
   // (the twiddle table in LDS only when it fits beside the columns, else it
   // is read through the caches)
   // Preference: a tile of 16 or 32 columns (rows of 128 B or more) that
-  // lets three workgroups share a CU (measured faster at cfg2's shape),
-  // else the widest valid tile at two per CU.
+  // lets four, else three workgroups share a CU (float32 only: the float64
+  // pencils need more than a quarter of the registers), else the widest
+  // valid tile at two per CU.
   const size_t twb = (size_t)g.nt * csize, gb = (size_t)g.nt * sizeof(double);
-  const size_t budget3 = 53 * 1024;
-  for (int pass = 0; pass < 2; ++pass) {
-    const size_t lim = pass == 0 ? budget3 : budget;
-    for (int tx4 = 32; tx4 >= (pass == 0 ? 16 : 8); tx4 >>= 1) {
+  const size_t tiers[3] = {f64 ? 0 : (size_t)39 * 1024, (size_t)53 * 1024, budget};
+  for (int pass = 0; pass < 3; ++pass) {
+    const size_t lim = tiers[pass];
+    for (int tx4 = 32; tx4 >= (pass < 2 ? 16 : 8); tx4 >>= 1) {
       const int ncol = tx4 / 2, tpc = NT / ncol, n1 = g.nt / tpc;
       if (tx4 / 2 >= g.S && tx4 > 8) continue;
       if (n1 < 4 || n1 > ept || n1 * tpc != g.nt) continue;

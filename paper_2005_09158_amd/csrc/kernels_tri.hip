@@ -40,7 +40,8 @@ __global__ __launch_bounds__(NT) void k_line_solve(T* __restrict__ spec, const d
   extern __shared__ __align__(16) unsigned char smraw[];
   T* sre = reinterpret_cast<T*>(smraw);
   T* sim = sre + TK * ldy;
-  const int k0 = blockIdx.x * TK, n = blockIdx.y, b = blockIdx.z;
+  const BlockPos bp = xcd_block();
+  const int k0 = bp.x * TK, n = bp.y, b = bp.z;
   const int nk = min(TK, sx - k0);
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
   bool vec = false;
