@@ -52,12 +52,17 @@ __device__ __forceinline__ void ldv(const Tin* p, double (&o)[V]) {
 template <typename Tin, int V>
 __device__ __forceinline__ void points_and_k(const Tin* un, int x, int y, int nx, int ny,
                                              const Stencil& st, double (&u)[V], double (&ku)[V]) {
+  // Every load is issued unconditionally (a missing neighbour reads the
+  // point itself and is then left out), so that they are all in flight
+  // together instead of one after another behind divergent branches.
   const Tin* c = un + (int64_t)y * nx + x;
+  const int dup = y > 0 ? nx : 0, ddn = y < ny - 1 ? nx : 0;
+  const int dl = x > 0 ? 1 : 0, dr = x + V < nx ? V : V - 1;
   double up[V], dn[V];
   ldv<Tin, V>(c, u);
-  if (y > 0) ldv<Tin, V>(c - nx, up);
-  if (y < ny - 1) ldv<Tin, V>(c + nx, dn);
-  const double lft = x > 0 ? ld(c - 1) : 0.0, rgt = x + V < nx ? ld(c + V) : 0.0;
+  ldv<Tin, V>(c - dup, up);
+  ldv<Tin, V>(c + ddn, dn);
+  const double lft = ld(c - dl), rgt = ld(c + dr);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     double k = st.d * u[v];
@@ -76,6 +81,30 @@ __device__ __forceinline__ void point_and_k(const Tin* un, int x, int y, int nx,
   points_and_k<Tin, 1>(un, x, y, nx, ny, st, uu, kk);
   u = uu[0];
   ku = kk[0];
+}
+
+// One step of the march: r = c1_0 u_0 + c2_0 K u_0 + c1_1 u_1 + ... at V
+// points, y = b - r (or r), then shift the history.
+template <int V>
+__device__ __forceinline__ void march_step(const double (&u0)[V], const double (&k0)[V],
+                                           const double (&bv)[V], bool hasb, int L, double c10,
+                                           double c11, double c12, double c20, double c21,
+                                           double c22, double (&u1)[V], double (&k1)[V],
+                                           double (&u2)[V], double (&k2)[V], double* dst) {
+  double r[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    r[v] = c10 * u0[v] + c20 * k0[v] + c11 * u1[v] + c21 * k1[v];
+    if (L > 2) r[v] += c12 * u2[v] + c22 * k2[v];
+    if (hasb) r[v] = bv[v] - r[v];
+    u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = u0[v]; k1[v] = k0[v];
+  }
+  if constexpr (V == 1) {
+    dst[0] = r[0];
+  } else {
+#pragma unroll
+    for (int h = 0; h < V; h += 2) *reinterpret_cast<double2*>(dst + h) = double2{r[h], r[h + 1]};
+  }
 }
 
 // dir = +1: y = A u ;  dir = -1: y = A^T u (stencil already transposed by the
@@ -110,27 +139,24 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
 #pragma unroll
     for (int v = 0; v < V; ++v) { u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = uu[v]; k1[v] = kk[v]; }
   }
-  for (int i = 0; i < nend - nbeg; ++i) {
-    const int n = (dir > 0) ? (nbeg + i) : (nend - 1 - i);
-    double u0[V], k0[V];
-    points_and_k<Tin, V>(ub + (int64_t)n * S, x, y, nx, ny, st, u0, k0);
-    const int64_t off = (int64_t)n * S + s;
-    double bv[V];
-    if (bb) ldv<double, V>(bb + off, bv);
-    double r[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      r[v] = c10 * u0[v] + c20 * k0[v] + c11 * u1[v] + c21 * k1[v];
-      if (L > 2) r[v] += c12 * u2[v] + c22 * k2[v];
-      if (bb) r[v] = bv[v] - r[v];
-      u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = u0[v]; k1[v] = k0[v];
+  // two time steps per iteration, all of both steps' loads issued first (the
+  // second step of an odd tail re-reads the first and is not stored)
+  const int cnt = nend - nbeg;
+  for (int i = 0; i < cnt; i += 2) {
+    const int nA = (dir > 0) ? (nbeg + i) : (nend - 1 - i);
+    const int iB = min(i + 1, cnt - 1);
+    const int nB = (dir > 0) ? (nbeg + iB) : (nend - 1 - iB);
+    double uA[V], kA[V], uB[V], kB[V], bA[V], bB[V];
+    points_and_k<Tin, V>(ub + (int64_t)nA * S, x, y, nx, ny, st, uA, kA);
+    points_and_k<Tin, V>(ub + (int64_t)nB * S, x, y, nx, ny, st, uB, kB);
+    const int64_t offA = (int64_t)nA * S + s, offB = (int64_t)nB * S + s;
+    if (bb) {
+      ldv<double, V>(bb + offA, bA);
+      ldv<double, V>(bb + offB, bB);
     }
-    if constexpr (V == 1) {
-      yb[off] = r[0];
-    } else {
-#pragma unroll
-      for (int h = 0; h < V; h += 2) *reinterpret_cast<double2*>(yb + off + h) = double2{r[h], r[h + 1]};
-    }
+    march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA);
+    if (i + 1 < cnt)
+      march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB);
   }
 }
 
