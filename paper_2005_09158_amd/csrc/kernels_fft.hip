@@ -38,6 +38,14 @@ template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x
 // multiply by -i
 template <typename C> __device__ __forceinline__ C cmi(C a) { return C{a.y, -a.x}; }
 
+// Twiddle W^m (0 <= m < 2 half) from a table of its first half, W^k for
+// k < half: W^{k + half} = -W^k.  Halving the table keeps it in LDS beside
+// the widest tiles.
+template <typename C> __device__ __forceinline__ C twid(const C* t, int m, int half) {
+  const C w = t[m & (half - 1)];
+  return (m & half) ? C{-w.x, -w.y} : w;
+}
+
 constexpr int NT = 256;
 
 // Column bases in LDS: a uniform stride, or the sub-columns of the four-step
@@ -55,8 +63,9 @@ template <int LOGN1> struct ColSub {
 
 // In-place forward Stockham FFT of `ncol` columns of length Nt in LDS, column
 // c at sm + cm.base(c).  EPT = complex values held per thread in a pass
-// (>= ncol*Nt/NT).  tw[k * tws] = exp(-2 pi i k / Nt).
-template <typename T, int EPT, typename CM>
+// (>= ncol*Nt/NT).  tw[k * tws] = exp(-2 pi i k / Nt) for k * tws below half
+// the table (see twid).
+template <typename T, int EPT, typename CM, int NTH = NT>
 __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM cm, int Nt, int logNt,
                                             const typename V2<T>::t* __restrict__ tw, int tws = 1) {
   using C = typename V2<T>::t;
@@ -67,7 +76,7 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM 
     C v[EPT];
 #pragma unroll
     for (int i = 0; i < EPT / 2; ++i) {
-      int bf = threadIdx.x + i * NT;
+      int bf = threadIdx.x + i * NTH;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
         const C* src = sm + cm.base(col) + j;
@@ -78,7 +87,7 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT / 2; ++i) {
-      int bf = threadIdx.x + i * NT;
+      int bf = threadIdx.x + i * NTH;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
         // Ns == 1: no twiddle
@@ -93,11 +102,11 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM 
   }
   while (bits > 0) {  // radix-4 passes
     const int nb = Nt >> 2, lognb = logNt - 2, total = ncol * nb;
-    const int step = Nt / (Ns << 2);
+    const int step = Nt / (Ns << 2), half = (Nt * tws) >> 1;
     C v[EPT];
 #pragma unroll
     for (int i = 0; i < EPT / 4; ++i) {
-      int bf = threadIdx.x + i * NT;
+      int bf = threadIdx.x + i * NTH;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
         const C* src = sm + cm.base(col) + j;
@@ -110,15 +119,15 @@ __device__ __forceinline__ void fft_columns(typename V2<T>::t* sm, int ncol, CM 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT / 4; ++i) {
-      int bf = threadIdx.x + i * NT;
+      int bf = threadIdx.x + i * NTH;
       if (bf < total) {
         int col = bf >> lognb, j = bf & (nb - 1);
         int k = j & (Ns - 1);
         C v0 = v[4 * i], v1 = v[4 * i + 1], v2 = v[4 * i + 2], v3 = v[4 * i + 3];
         if (k) {
-          v1 = cmul(v1, tw[k * step * tws]);
-          v2 = cmul(v2, tw[2 * k * step * tws]);
-          v3 = cmul(v3, tw[3 * k * step * tws]);
+          v1 = cmul(v1, twid(tw, k * step * tws, half));
+          v2 = cmul(v2, twid(tw, 2 * k * step * tws, half));
+          v3 = cmul(v3, twid(tw, 3 * k * step * tws, half));
         }
         C t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = cmi(csub(v1, v3));
         C* dst = sm + cm.base(col) + ((j - k) << 2) + k;
@@ -141,10 +150,11 @@ template <> struct FftTraits<float> { static constexpr int EPT = 32; };
 template <> struct FftTraits<double> { static constexpr int EPT = 16; };
 
 
-// Copies the Nt-entry twiddle table into LDS behind the data columns.
+// Copies the first half of the Nt-entry twiddle table into LDS behind the
+// data columns (twid supplies the second half).
 template <typename C>
 __device__ __forceinline__ void stage_twiddles(C* smtw, const C* __restrict__ tw, int Nt) {
-  for (int i = threadIdx.x; i < Nt; i += NT) smtw[i] = tw[i];
+  for (int i = threadIdx.x; i < (Nt >> 1); i += blockDim.x) smtw[i] = tw[i];
 }
 
 // Reads the pair of real time samples (s, s+1) at one time row; columns past
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
   const double* xb = x + (int64_t)b * Nt * S;
   const double sc = bscale ? bscale[b] : 1.0;
   const bool vec = (S & 1) == 0;
-  double* smg = reinterpret_cast<double*>(smtw + Nt);   // Gamma
+  double* smg = reinterpret_cast<double*>(smtw + (Nt >> 1));   // Gamma
   // 1. stage: lane j of a row reads real columns (2j, 2j+1) with one 16-byte
   //    load and stores them as the complex value r_2j + i r_2j+1 of column j.
   //    A tile's loads fit one batch ((TX/2) Nt <= EPT NT), all issued before
@@ -397,27 +407,27 @@ __device__ __forceinline__ void fourstep_pass1(typename V2<T>::t (&c)[N1], typen
 #pragma unroll
   for (int q = 0; q < N1; ++q) {
     C xq = c[brev<N1>(q)];
-    if (q) xq = cmul(xq, smtw[(r * q) & (Nt - 1)]);
+    if (q) xq = cmul(xq, twid(smtw, (r * q) & (Nt - 1), Nt >> 1));
     sm[j * cstr + q * ldc + r] = xq;
   }
 }
 
-template <typename T, int TX, int N1>
-__global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x, T* __restrict__ spec,
+template <typename T, int TX, int N1, int NTH = NT>
+__global__ __launch_bounds__(NTH, NTH / 128) void k_fft4_fwd(const double* __restrict__ x, T* __restrict__ spec,
                                                     const double* __restrict__ gam,
                                                     const double* __restrict__ bscale,
                                                     const typename V2<T>::t* __restrict__ tw, int Nt,
                                                     int S, int sx, int sy, int reverse, int gam_lds,
                                                     int tw_lds) {
   using C = typename V2<T>::t;
-  constexpr int NCOL = TX / 2, TPC = NT / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
+  constexpr int NCOL = TX / 2, TPC = NTH / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
   constexpr int LDC = TPC + 1;           // sub-column stride
   extern __shared__ __align__(16) unsigned char smraw[];
   C* sm = reinterpret_cast<C*>(smraw);
   const int cstr = N1 * LDC + 1;         // column stride (odd: columns fall in different banks)
   const int F = (Nt >> 1) + 1;
   C* smtw = sm + NCOL * cstr;
-  double* smg = reinterpret_cast<double*>(smtw + (tw_lds ? Nt : 0));
+  double* smg = reinterpret_cast<double*>(smtw + (tw_lds ? (Nt >> 1) : 0));
   const C* twp = tw_lds ? smtw : tw;     // twiddles in LDS, or through the caches
   const BlockPos bp = xcd_block();
   const int b = bp.y, s0 = bp.x * TX;
@@ -435,7 +445,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x
   }
   if (tw_lds) stage_twiddles(smtw, tw, Nt);
   if (gam_lds)
-    for (int i = threadIdx.x; i < Nt; i += NT) smg[i] = gam[i];
+    for (int i = threadIdx.x; i < Nt; i += NTH) smg[i] = gam[i];
   __syncthreads();
   C c[N1];
 #pragma unroll
@@ -446,7 +456,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x
   }
   fourstep_pass1<T, N1, TPC>(c, sm, twp, Nt, j, r, LDC, cstr);
   __syncthreads();
-  fft_columns<T, N1>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
+  fft_columns<T, N1, ColSub<LOGN1>, NTH>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
   // Hermitian split (as k_fft_fwd), Z[k] at (j, k mod N1) position k / N1
   if (s >= S) return;
   T* specb = spec + (int64_t)b * F * sy * 2 * sx;
@@ -476,15 +486,15 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_fwd(const double* __restrict__ x
   }
 }
 
-template <typename T, int TX, int N1, typename Tout>
-__global__ __launch_bounds__(NT, 2) void k_fft4_inv(const T* __restrict__ spec, Tout* __restrict__ z,
+template <typename T, int TX, int N1, typename Tout, int NTH = NT>
+__global__ __launch_bounds__(NTH, NTH / 128) void k_fft4_inv(const T* __restrict__ spec, Tout* __restrict__ z,
                                                     const double* __restrict__ invgam,
                                                     const typename V2<T>::t* __restrict__ tw, int Nt,
                                                     int S, int sx, int sy, int accumulate, int reverse,
                                                     int tw_lds) {
   using C = typename V2<T>::t;
   using O2 = typename Out2<Tout>::t;
-  constexpr int NCOL = TX / 2, TPC = NT / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
+  constexpr int NCOL = TX / 2, TPC = NTH / NCOL, LOGN1 = Log2<N1>::v, LOGTPC = Log2<TPC>::v;
   constexpr int LDC = TPC + 1;
   constexpr int KU = N1 / 2 + 1;         // spectrum rows k = r + TPC u < F
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -548,7 +558,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_inv(const T* __restrict__ spec, 
   __syncthreads();
   fourstep_pass1<T, N1, TPC>(c, sm, twp, Nt, j, r, LDC, cstr);
   __syncthreads();
-  fft_columns<T, N1>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
+  fft_columns<T, N1, ColSub<LOGN1>, NTH>(sm, NCOL * N1, ColSub<LOGN1>{LDC, cstr}, TPC, LOGTPC, twp, N1);
   // 3. z = conj(fft(conj Z)) / Nt with Gamma^{-1}; sample n at (j, n mod N1) position n / N1
   if (s >= S) return;
   Tout* zb = z + (int64_t)b * Nt * S;
@@ -580,13 +590,13 @@ __global__ __launch_bounds__(NT, 2) void k_fft4_inv(const T* __restrict__ spec, 
 
 // LDS bytes of the four-step kernels' columns (stride N1 (TPC + 1) + 1);
 // the twiddle and Gamma tables follow when they fit.
-inline size_t fourstep_cols(int tx, int nt, size_t csize) {
-  const int ncol = tx / 2, tpc = NT / ncol, n1 = nt / tpc;
+inline size_t fourstep_cols(int tx, int nt, size_t csize, int nth = NT) {
+  const int ncol = tx / 2, tpc = nth / ncol, n1 = nt / tpc;
   return (size_t)ncol * ((size_t)n1 * (tpc + 1) + 1) * csize;
 }
 
 // n1 > 0: four-step kernels; lds_inv: bytes of the inverse (no Gamma table)
-struct FftShape { int TX; size_t lds; bool gam_lds; int n1; bool tw_lds; size_t lds_inv; };
+struct FftShape { int TX; size_t lds; bool gam_lds; int n1; bool tw_lds; size_t lds_inv; int nth; };
 
 // Widest tile (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex
 // columns of Nt+1 entries plus the twiddle table -- lets two workgroups share
@@ -600,7 +610,7 @@ FftShape choose_shape(const Plan& pl) {
   int TX = 32;
   // columns and twiddles; the forward kernel adds the Gamma table when it
   // fits beside them without narrowing the tile
-  auto lds = [&](int tx) { return (size_t)(tx / 2) * (g.nt + 1) * csize + (size_t)g.nt * csize; };
+  auto lds = [&](int tx) { return (size_t)(tx / 2) * (g.nt + 1) * csize + (size_t)(g.nt / 2) * csize; };
   while (TX > 2 && (lds(TX) > budget || (int64_t)(TX / 2) * g.nt > (int64_t)ept * NT)) TX >>= 1;
   while (TX > 2 && TX / 2 >= g.S) TX >>= 1;  // no wider than the spatial extent needs
   // four-step form when the pencil length N1 = Nt / TPC is 4 .. EPT and the
@@ -611,25 +621,29 @@ FftShape choose_shape(const Plan& pl) {
   // lets four, else three workgroups share a CU (float32 only: the float64
   // pencils need more than a quarter of the registers), else the widest
   // valid tile at two per CU.
-  const size_t twb = (size_t)g.nt * csize, gb = (size_t)g.nt * sizeof(double);
+  const size_t twb = (size_t)(g.nt / 2) * csize, gb = (size_t)g.nt * sizeof(double);
   const size_t tiers[3] = {f64 ? 0 : (size_t)39 * 1024, (size_t)53 * 1024, budget};
+  // At two per CU a 512-thread workgroup (half the pencil per thread, twice
+  // the waves) is tried first: measured faster at Nt = 2048.
   for (int pass = 0; pass < 3; ++pass) {
     const size_t lim = tiers[pass];
-    for (int tx4 = 32; tx4 >= (pass < 2 ? 16 : 8); tx4 >>= 1) {
-      const int ncol = tx4 / 2, tpc = NT / ncol, n1 = g.nt / tpc;
-      if (tx4 / 2 >= g.S && tx4 > 8) continue;
-      if (n1 < 4 || n1 > ept || n1 * tpc != g.nt) continue;
-      const size_t cols = fourstep_cols(tx4, g.nt, csize);
-      if (cols > lim) continue;
-      const bool twl = cols + twb <= lim;
-      const size_t inv = cols + (twl ? twb : 0);
-      const bool gl = inv + gb <= lim;
-      return FftShape{tx4, inv + (gl ? gb : 0), gl, n1, twl, inv};
-    }
+    for (int tx4 = 32; tx4 >= (pass < 2 ? 16 : 8); tx4 >>= 1)
+      for (int nth = (pass == 2 ? 2 * NT : NT); nth >= NT; nth >>= 1) {
+        const int ncol = tx4 / 2, tpc = nth / ncol, n1 = g.nt / tpc;
+        if (tx4 / 2 >= g.S && tx4 > 8) continue;
+        if (n1 < 4 || n1 > ept || n1 * tpc != g.nt) continue;
+        if (nth > NT && (tx4 > 16 || n1 < 8 || n1 > 16)) continue;   // instantiated shapes
+        const size_t cols = fourstep_cols(tx4, g.nt, csize, nth);
+        if (cols > lim) continue;
+        const bool twl = cols + twb <= lim;
+        const size_t inv = cols + (twl ? twb : 0);
+        const bool gl = inv + gb <= lim;
+        return FftShape{tx4, inv + (gl ? gb : 0), gl, n1, twl, inv, nth};
+      }
   }
   const size_t with_gam = lds(TX) + gb;
   const bool gam_lds = with_gam <= budget;
-  return FftShape{TX, gam_lds ? with_gam : lds(TX), gam_lds, 0, true, lds(TX)};
+  return FftShape{TX, gam_lds ? with_gam : lds(TX), gam_lds, 0, true, lds(TX), NT};
 }
 
 template <typename T>
@@ -641,21 +655,24 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
   while ((1 << logNt) < g.nt) ++logNt;
   dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
   if (sh.n1 > 0) {
-#define PD_FWD4(W, N)                                                                      \
-  if (sh.TX == W && sh.n1 == N) {                                                          \
-    hipFuncSetAttribute((const void*)k_fft4_fwd<T, W, N>,                                  \
+#define PD_FWD4T(W, N, H)                                                                  \
+  if (sh.TX == W && sh.n1 == N && sh.nth == H) {                                           \
+    hipFuncSetAttribute((const void*)k_fft4_fwd<T, W, N, H>,                               \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
-    k_fft4_fwd<T, W, N><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt,      \
-                                                 (int)g.S, g.sx, g.sy, reverse, sh.gam_lds, \
-                                                 sh.tw_lds);                               \
+    k_fft4_fwd<T, W, N, H><<<grid, H, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt,    \
+                                                   (int)g.S, g.sx, g.sy, reverse,          \
+                                                   sh.gam_lds, sh.tw_lds);                 \
     return;                                                                                \
   }
+#define PD_FWD4(W, N) PD_FWD4T(W, N, NT)
     PD_FWD4(8, 4) PD_FWD4(8, 8) PD_FWD4(8, 16) PD_FWD4(16, 4) PD_FWD4(16, 8) PD_FWD4(16, 16)
     PD_FWD4(32, 4) PD_FWD4(32, 8) PD_FWD4(32, 16)
     if constexpr (FftTraits<T>::EPT >= 32) {
       PD_FWD4(8, 32) PD_FWD4(16, 32) PD_FWD4(32, 32)
     }
+    PD_FWD4T(8, 8, 512) PD_FWD4T(8, 16, 512) PD_FWD4T(16, 8, 512) PD_FWD4T(16, 16, 512)
 #undef PD_FWD4
+#undef PD_FWD4T
   }
 #define PD_FWD(W)                                                                          \
   case W:                                                                                  \
@@ -681,21 +698,24 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
   dim3 grid((unsigned)((g.S + sh.TX - 1) / sh.TX), g.B);
   if (sh.n1 > 0) {
     const size_t lds4 = sh.lds_inv;
-#define PD_INV4(W, N)                                                                      \
-  if (sh.TX == W && sh.n1 == N) {                                                          \
-    hipFuncSetAttribute((const void*)k_fft4_inv<T, W, N, Tout>,                            \
+#define PD_INV4T(W, N, H)                                                                  \
+  if (sh.TX == W && sh.n1 == N && sh.nth == H) {                                           \
+    hipFuncSetAttribute((const void*)k_fft4_inv<T, W, N, Tout, H>,                         \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);            \
-    k_fft4_inv<T, W, N, Tout><<<grid, NT, lds4, s>>>(spec, z, pl.d_invgam, tw, g.nt,       \
-                                                     (int)g.S, g.sx, g.sy, accumulate,     \
-                                                     reverse, sh.tw_lds);                  \
+    k_fft4_inv<T, W, N, Tout, H><<<grid, H, lds4, s>>>(spec, z, pl.d_invgam, tw, g.nt,     \
+                                                       (int)g.S, g.sx, g.sy, accumulate,   \
+                                                       reverse, sh.tw_lds);                \
     return;                                                                                \
   }
+#define PD_INV4(W, N) PD_INV4T(W, N, NT)
     PD_INV4(8, 4) PD_INV4(8, 8) PD_INV4(8, 16) PD_INV4(16, 4) PD_INV4(16, 8) PD_INV4(16, 16)
     PD_INV4(32, 4) PD_INV4(32, 8) PD_INV4(32, 16)
     if constexpr (FftTraits<T>::EPT >= 32) {
       PD_INV4(8, 32) PD_INV4(16, 32) PD_INV4(32, 32)
     }
+    PD_INV4T(8, 8, 512) PD_INV4T(8, 16, 512) PD_INV4T(16, 8, 512) PD_INV4T(16, 16, 512)
 #undef PD_INV4
+#undef PD_INV4T
   }
 #define PD_INV(W)                                                                          \
   case W:                                                                                  \

@@ -88,8 +88,18 @@ LineShape line_shape(const Plan& pl) {
   int ldy = P * (R + 1);
   if ((ldy & 1) == 0) ldy += 1;
   size_t esz = (pl.prec == Prec::F64) ? 8 : 4;
+  // Waves per SIMD that the kernel's registers allow (compiler-reported VGPRs
+  // of the instantiations: float 70 / 117 / 214 at R = 4 / 8 / 16, double
+  // 98 (P = 1) / 168 / 248 at R = 4 / 4 / 8).  A workgroup is one wave per
+  // SIMD, so the tile is sized for that many workgroups per CU: the loads of
+  // some overlap the solves of the others.
+  int occ;
+  if (pl.prec == Prec::F64) occ = (R == 4) ? (P == 1 ? 4 : 3) : (R == 8 ? 2 : 1);
+  else occ = (R == 4) ? 7 : (R == 8 ? 4 : (R == 16 ? 2 : 1));
+  const size_t lim = std::min<size_t>(80 * 1024, (size_t)158 * 1024 / occ);
   int TK = 16;
-  while (TK > 1 && (size_t)2 * TK * ldy * esz > 80 * 1024) TK >>= 1;
+  while (TK > 4 && (size_t)2 * TK * ldy * esz > lim) TK >>= 1;
+  while (TK > 1 && (size_t)2 * TK * ldy * esz > 158 * 1024) TK >>= 1;
   while (TK > 1 && TK / 2 >= g.sx) TK >>= 1;
   return LineShape{R, P, TK, ldy, (size_t)2 * TK * ldy * esz};
 }
