@@ -16,6 +16,9 @@ namespace pd {
 namespace {
 thread_local std::string g_last_error;
 constexpr int MAXV = 33;   // Krylov slots per right-hand side (restart <= 32)
+// Largest component along the Krylov basis, relative to the vector's norm,
+// that the first Gram-Schmidt pass may leave without a second pass.
+constexpr double kReorthTol = 1e-12;
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -508,6 +511,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     hipMemcpyAsync(sm.sigma, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, s);
     std::vector<int> kk(B, 0);   // columns used per right-hand side
     std::vector<char> live = active;
+    bool second = true;
     int j = 0;
     for (; j < m; ++j) {
       // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a))
@@ -518,16 +522,28 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       {
         double* w = Vj(j + 1);
         // classical Gram-Schmidt, two passes; the second pass's dots come from the
-        // first pass's update kernel, the final norm by Pythagoras
+        // first pass's update kernel, the final norm by Pythagoras.  The second
+        // update is applied only when some live right-hand side keeps a
+        // component along the basis above kReorthTol of its norm after the
+        // first pass (selective reorthogonalisation): otherwise the vector is
+        // already orthogonal to that accuracy and is kept as it is.
         timed_dot(pl, V, vs, j + 1, w, sm.partial, s);
         timed_reduce(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
-        timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
         hipMemcpyAsync(hbuf.data(), sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(hbuf.data() + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
                        hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);
+        second = false;
+        for (int i = 0; i < B; ++i) {
+          if (!live[i]) continue;
+          const double* h2 = hbuf.data() + (size_t)B * MAXV + (size_t)i * MAXV;
+          double mx = 0;
+          for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
+          if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
+        }
+        if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
       }
       ++iters;
       double est_max = 0;
@@ -537,12 +553,13 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         const double* h2 = hbuf.data() + (size_t)B * MAXV + (size_t)i * MAXV;
         double* Hc = H.data() + (size_t)i * (m + 1) * m;   // column-major (m+1) x m
         for (int q = 0; q <= j; ++q) {
-          double v = h1[q] + h2[q];
+          double v = h1[q] + (second ? h2[q] : 0.0);
           if (!std::isfinite(v)) { set_error("non-finite Krylov scalar"); return PD_ERR_NONFINITE; }
           Hc[(size_t)j * (m + 1) + q] = v;
         }
         double nn = h2[j + 1];
-        for (int q = 0; q <= j; ++q) nn -= h2[q] * h2[q];
+        if (second)
+          for (int q = 0; q <= j; ++q) nn -= h2[q] * h2[q];
         double hn = nn > 0 ? std::sqrt(nn) : 0.0;
         Hc[(size_t)j * (m + 1) + j + 1] = hn;
         if (!live[i]) { sig[(size_t)i * MAXV + j + 1] = 0.0; continue; }
