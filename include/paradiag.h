@@ -187,7 +187,12 @@ paradiag_status paradiag_get_xbasis(paradiag_plan plan, int32_t adjoint, double*
 paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* lam2);
 
 /* Stage timing.  When enabled, every later call records HIP events around
- * each kernel launch on the call's own stream.  paradiag_get_stage_times
+ * each kernel launch of the selected stages on the call's own stream.
+ * paradiag_set_timing: enable = 0 turns timing off, 1 times every stage,
+ * and a value >= 2 is a stage mask shifted left by one (bit s + 1 selects
+ * PD_STAGE s), so that a single stage can be timed with the fewest events;
+ * values with bits beyond the last stage return PD_ERR_INVALID.
+ * paradiag_get_stage_times
  * returns, per stage (PD_STAGE_*), the summed milliseconds, the launch count
  * and the algorithmic work of those launches since the last reset: bytes
  * that must cross HBM at least once (inputs read once, outputs written once)

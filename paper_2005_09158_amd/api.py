@@ -165,8 +165,18 @@ class ParaDiag:
                            rtol, max_iter, restart, x0)
 
     # ----------------------------------------------------------- inspection
-    def set_timing(self, enable: bool) -> None:
-        _lib.check(self.lib.paradiag_set_timing(self.plan, int(enable)), "paradiag_set_timing")
+    def set_timing(self, enable, stages=None) -> None:
+        """Turn stage timing on or off; with `stages` (names as in stage_times),
+        only those stages are timed."""
+        if not enable:
+            code = 0
+        elif stages is None:
+            code = 1
+        else:
+            code = 0
+            for name in stages:
+                code |= 1 << (_lib.STAGES.index(name) + 1)
+        _lib.check(self.lib.paradiag_set_timing(self.plan, code), "paradiag_set_timing")
 
     def stage_times(self, reset: bool = True) -> dict:
         """{stage: (ms, launches, algorithmic bytes, flops)} since the last reset."""

@@ -234,7 +234,7 @@ struct Timed {
   hipEvent_t a = nullptr, b = nullptr;
   Timed(Plan& p, int st, hipStream_t str, double bytes = 0, double flops = 0)
       : pl(p), stage(st), s(str) {
-    if (!pl.timer.enabled) return;
+    if (!pl.timer.enabled || !((pl.timer.mask >> stage) & 1u)) return;
     pl.timer.bytes[stage] += bytes;
     pl.timer.flops[stage] += flops;
     a = take();
@@ -248,7 +248,7 @@ struct Timed {
     return e;
   }
   ~Timed() {
-    if (!pl.timer.enabled) return;
+    if (!a) return;
     hipEventRecord(b, s);
     pl.timer.pending.push_back({stage, a, b});
   }
@@ -290,12 +290,13 @@ static double sweep_flops(const Plan& pl) {
   return 8.0 * g.B * g.F * g.sy * 0.5 * (double)g.sx * (g.sx - 1);
 }
 
-static void apply_prec(Plan& pl, int variant, const double* in, const double* bscale, void* out,
-                       bool out_f32, int accumulate, hipStream_t s) {
+// bscale: per right-hand side factor on the input (entry b * bstride), or null
+static void apply_prec(Plan& pl, int variant, const double* in, const double* bscale, int bstride,
+                       void* out, bool out_f32, int accumulate, hipStream_t s) {
   const SpaceOp& op = pl.op[variant];
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
-  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, pl.spec_a, variant, s); }
+  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, bstride, pl.spec_a, variant, s); }
   if (pl.p.dim == 2) {
     { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
     {
@@ -365,15 +366,38 @@ static void timed_reduce(Plan& pl, const double* part, int nv, const double* sig
   reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s);
 }
 namespace {
-void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s) {
-  timed_dot(pl, v, 0, 1, v, sm.partial, s);
+// Pinned host staging of the solvers' small transfers: [norms | h1 h2 | sigma | y],
+// B * MAXV doubles each.  Pinned copies run asynchronously, so a region is
+// rewritten by the host only after a stream synchronisation that follows
+// its last copy (every Arnoldi step and every norm ends with one).
+double* pinned(Plan& pl) {
+  const size_t n = (size_t)5 * pl.g.B * MAXV;
+  if (pl.pin_n < n) {
+    if (pl.pin) hipHostFree(pl.pin);
+    pl.pin = nullptr;
+    pl.pin_n = 0;
+    if (hipHostMalloc((void**)&pl.pin, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+      pl.pin = nullptr;
+      return nullptr;
+    }
+    pl.pin_n = n;
+  }
+  return pl.pin;
+}
+
+void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s) {
   timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s);
-  std::vector<double> tmp((size_t)pl.g.B * MAXV);
-  hipMemcpyAsync(tmp.data(), sm.nrm, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost, s);
+  double* tmp = pl.pin;   // norms region
+  hipMemcpyAsync(tmp, sm.nrm, sizeof(double) * pl.g.B * MAXV, hipMemcpyDeviceToHost, s);
   hipStreamSynchronize(s);
   out.resize(pl.g.B);
   // |.| keeps a NaN visible (std::max(0, NaN) would hide it)
   for (int b = 0; b < pl.g.B; ++b) out[b] = std::sqrt(std::fabs(tmp[(size_t)b * MAXV]));
+}
+
+void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s) {
+  timed_dot(pl, v, 0, 1, v, sm.partial, s);
+  norms_from(pl, sm, out, s);
 }
 
 }  // namespace
@@ -402,19 +426,32 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   const bool zf32 = pl.prec != Prec::F64;
   const size_t zb = zf32 ? 4 : 8;
   Small sm = carve_small(pl, p);
+  if (!pinned(pl)) { set_error("pinned host staging allocation failed"); return PD_ERR_HIP; }
+  // FGMRES from a zero guess takes V_0 = b: copy and norm in one pass
+  const bool fused_start = o->mode == PD_MODE_FGMRES && !o->use_x0;
   std::vector<double> bn;
-  norms(pl, b, sm, bn, s);
+  if (fused_start) {
+    Timed t(pl, PD_STAGE_OTHER, s, 16.0 * g.NA, 2.0 * g.NA);
+    copy_sq(pl, b, (double*)p, sm.partial, s);
+  } else {
+    timed_dot(pl, b, 0, 1, b, sm.partial, s);
+  }
+  norms_from(pl, sm, bn, s);
   for (int i = 0; i < B; ++i)
     if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
   std::vector<int> it_rhs(B, 0);
   std::vector<double> res(B, 0.0);
   int iters = 0;
   int hist_len = 0;
+  // false while u is implicitly zero (FGMRES from a zero guess has not yet
+  // written it): the first solution update then overwrites instead of adding
+  bool u_valid = true;
   auto push_hist = [&](double v) {
     if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
     ++hist_len;
   };
   auto finish = [&](bool conv) -> paradiag_status {
+    if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
     double mx = 0;
     for (int i = 0; i < B; ++i) mx = std::max(mx, res[i]);
     if (info) {
@@ -441,7 +478,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   };
 
   if (o->mode == PD_MODE_DIRECT) {
-    apply_prec(pl, variant, b, nullptr, u, false, 0, s);
+    apply_prec(pl, variant, b, nullptr, 0, u, false, 0, s);
     iters = 1;
     for (int i = 0; i < B; ++i) it_rhs[i] = 1;
     // residual of the result with respect to A (reported, not iterated)
@@ -467,7 +504,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       push_hist(*std::max_element(res.begin(), res.end()));
       if (all) return finish(true);
       if (iters >= o->max_iter) return finish(false);
-      apply_prec(pl, variant, r, nullptr, u, false, 1, s);
+      apply_prec(pl, variant, r, nullptr, 0, u, false, 1, s);
       ++iters;
       for (int i = 0; i < B; ++i)
         if (res[i] > o->rtol) it_rhs[i] = iters;
@@ -484,17 +521,26 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   auto Vj = [&](int j) { return V + (int64_t)j * vs; };
   auto Zj = [&](int j) { return (void*)(Z + (size_t)j * zs * zb); };
 
-  if (!o->use_x0) fill_zero(u, g.NA, s);
+  if (!o->use_x0) u_valid = false;
   std::vector<double> H((size_t)B * (m + 1) * m), gv((size_t)B * (m + 1)), cs((size_t)B * m),
-      sn((size_t)B * m), sig((size_t)B * MAXV), hbuf((size_t)B * MAXV * 5), yv((size_t)B * MAXV);
-  std::vector<double> nr, bs(B);   // host staging buffers live across async copies
+      sn((size_t)B * m);
+  // pinned staging (see pinned): Hessenberg columns, Krylov scales, LSQ solution
+  double* hbuf = pl.pin + (size_t)B * MAXV;
+  double* sig = pl.pin + (size_t)3 * B * MAXV;
+  double* yv = pl.pin + (size_t)4 * B * MAXV;
+  std::vector<double> nr;
   bool first = true;
   while (true) {
-    // residual of the current iterate into V_0
-    if (first && !o->use_x0) copy_vec(b, Vj(0), g.NA, s);
-    else apply_A(pl, variant, u, false, b, Vj(0), s);
+    // residual of the current iterate into V_0 (from a zero guess V_0 = b,
+    // copied with its norm at the start)
+    if (first && fused_start) {
+      nr = bn;
+    } else {
+      if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
+      apply_A(pl, variant, u, false, b, Vj(0), s);
+      norms(pl, Vj(0), sm, nr, s);
+    }
     first = false;
-    norms(pl, Vj(0), sm, nr, s);
     bool all = rel(nr);
     for (int i = 0; i < B; ++i)
       if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
@@ -503,21 +549,20 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     if (iters >= o->max_iter) return finish(false);
     std::vector<char> active(B);
     for (int i = 0; i < B; ++i) active[i] = res[i] > o->rtol && nr[i] > 0;
-    std::fill(sig.begin(), sig.end(), 0.0);
+    std::fill(sig, sig + (size_t)B * MAXV, 0.0);
     for (int i = 0; i < B; ++i) {
       if (active[i]) sig[(size_t)i * MAXV] = 1.0 / nr[i];
       gv[(size_t)i * (m + 1)] = nr[i];
     }
-    hipMemcpyAsync(sm.sigma, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
     std::vector<int> kk(B, 0);   // columns used per right-hand side
     std::vector<char> live = active;
     bool second = true;
     int j = 0;
     for (; j < m; ++j) {
-      // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a))
-      for (int i = 0; i < B; ++i) bs[i] = sig[(size_t)i * MAXV + j];
-      hipMemcpyAsync(sm.y, bs.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-      apply_prec(pl, variant, Vj(j), sm.y, Zj(j), zf32, 0, s);
+      // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a) and
+      // read from the device copy of the scales, entry i * MAXV + j)
+      apply_prec(pl, variant, Vj(j), sm.sigma + j, MAXV, Zj(j), zf32, 0, s);
       apply_A(pl, variant, Zj(j), zf32, nullptr, Vj(j + 1), s);
       {
         double* w = Vj(j + 1);
@@ -531,14 +576,14 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         timed_reduce(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
-        hipMemcpyAsync(hbuf.data(), sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(hbuf.data() + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
+        hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hbuf + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
                        hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);
         second = false;
         for (int i = 0; i < B; ++i) {
           if (!live[i]) continue;
-          const double* h2 = hbuf.data() + (size_t)B * MAXV + (size_t)i * MAXV;
+          const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
           double mx = 0;
           for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
           if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
@@ -549,8 +594,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       double est_max = 0;
       bool any_live = false;
       for (int i = 0; i < B; ++i) {
-        const double* h1 = hbuf.data() + (size_t)i * MAXV;
-        const double* h2 = hbuf.data() + (size_t)B * MAXV + (size_t)i * MAXV;
+        const double* h1 = hbuf + (size_t)i * MAXV;
+        const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
         double* Hc = H.data() + (size_t)i * (m + 1) * m;   // column-major (m+1) x m
         for (int q = 0; q <= j; ++q) {
           double v = h1[q] + (second ? h2[q] : 0.0);
@@ -591,17 +636,17 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       }
       push_hist(est_max);
       if (!any_live || iters >= o->max_iter || j + 1 == m) { ++j; break; }
-      hipMemcpyAsync(sm.sigma, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, s);
+      hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
     }
     // solve the triangular systems and update x
-    std::fill(yv.begin(), yv.end(), 0.0);
+    std::fill(yv, yv + (size_t)B * MAXV, 0.0);
     int kmax = 0;
     for (int i = 0; i < B; ++i) {
       int k = kk[i];
       kmax = std::max(kmax, k);
       const double* Hc = H.data() + (size_t)i * (m + 1) * m;
       const double* gg = gv.data() + (size_t)i * (m + 1);
-      double* y = yv.data() + (size_t)i * MAXV;
+      double* y = yv + (size_t)i * MAXV;
       for (int q = k - 1; q >= 0; --q) {
         double acc = gg[q];
         for (int c = q + 1; c < k; ++c) acc -= Hc[(size_t)c * (m + 1) + q] * y[c];
@@ -610,9 +655,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       }
     }
     if (kmax > 0) {
-      hipMemcpyAsync(sm.y, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s);
+      hipMemcpyAsync(sm.y, yv, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
       Timed t(pl, PD_STAGE_OTHER, s, (double)g.NA * (16.0 + kmax * (double)zb), 2.0 * g.NA * kmax);
-      x_update(pl, Z, zf32, zs, kmax, sm.y, u, s);
+      x_update(pl, Z, zf32, zs, kmax, sm.y, u, !u_valid, s);
+      u_valid = true;
     }
   }
 }
@@ -672,6 +718,7 @@ void paradiag_destroy(paradiag_plan plan) {
   if (!pl) return;
   for (auto& r : pl->timer.pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
   for (auto e : pl->timer.pool) hipEventDestroy(e);
+  if (pl->pin) hipHostFree(pl->pin);
   delete pl;
 }
 
@@ -876,7 +923,7 @@ paradiag_status paradiag_apply_precond(paradiag_plan plan, const double* r, doub
   if (!r || !z) { set_error("NULL vector"); return PD_ERR_INVALID; }
   size_t nb = sizeof(double) * (size_t)pl->g.NA;
   if (r != z && overlap(r, nb, z, nb)) { set_error("r and z partially overlap"); return PD_ERR_INVALID; }
-  apply_prec(*pl, 0, r, nullptr, z, false, 0, (hipStream_t)stream);
+  apply_prec(*pl, 0, r, nullptr, 0, z, false, 0, (hipStream_t)stream);
   return check_hip("apply_precond");
 }
 
@@ -938,7 +985,9 @@ paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* l
 paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable) {
   Plan* pl = reinterpret_cast<Plan*>(plan);
   if (!pl) { set_error("plan is NULL"); return PD_ERR_INVALID; }
+  if (enable < 0 || enable >= (2 << PD_NUM_STAGES)) { set_error("timing selector out of range"); return PD_ERR_INVALID; }
   pl->timer.enabled = enable != 0;
+  pl->timer.mask = enable == 1 ? (1u << PD_NUM_STAGES) - 1 : (unsigned)enable >> 1;
   return PD_OK;
 }
 

@@ -76,6 +76,7 @@ struct Workspace;
 
 struct StageTimer {
   bool enabled = false;
+  unsigned mask = 0;   // stages timed while enabled (bit = stage)
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
@@ -115,6 +116,9 @@ struct Plan {
   char* solver_base = nullptr;
   int num_cu = 256;                // compute units of the bound device (persistent grids)
   StageTimer timer;
+  // pinned host staging of the solvers' small transfers (Krylov scalars, norms)
+  double* pin = nullptr;
+  size_t pin_n = 0;
 };
 
 size_t spec_elem_bytes(Prec p);          // 8 (double) or 4 (float)
@@ -127,7 +131,7 @@ struct Launch { hipStream_t stream; };
 
 // Step-(a): spec = rfft_t(Gamma * scale_b * x) ; x float64 [B][nt][S].
 // reverse != 0 reads x with time reversed (adjoint).
-void fft_time_forward(const Plan& pl, const double* x, const double* bscale, void* spec,
+void fft_time_forward(const Plan& pl, const double* x, const double* bscale, int bstride, void* spec,
                       int reverse, hipStream_t s);
 // Step-(c): z = Gamma^{-1} irfft_t(spec) (float64 or float32 output), optional accumulate.
 void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, int accumulate,
@@ -158,7 +162,9 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
                 double* w, double* partial, int want_dots, hipStream_t s);
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
-              const double* y, double* x, hipStream_t s);
+              const double* y, double* x, bool overwrite, hipStream_t s);
+// dst = src per right-hand side, partial sums of src^2 into slot 0 (see multi_dot)
+void copy_sq(const Plan& pl, const double* src, double* dst, double* partial, hipStream_t s);
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);
 void fill_zero(double* dst, int64_t n, hipStream_t s);
 

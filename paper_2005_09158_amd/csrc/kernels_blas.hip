@@ -293,6 +293,26 @@ __global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int
   }
 }
 
+// dst[b] = src[b] and partial[b][chunk][0] = sum over the chunk of src^2:
+// the first Krylov vector and its norm from one read of the right-hand side.
+__global__ __launch_bounds__(NT) void k_copy_sq(const double* __restrict__ src, double* __restrict__ dst,
+                                                double* __restrict__ partial, int64_t N1, int chunks) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int64_t per = ((N1 + chunks - 1) / chunks + 1) & ~(int64_t)1;
+  const int64_t beg = c * per, end = min(N1, beg + per);
+  const double* sb = src + (int64_t)b * N1;
+  double* db = dst + (int64_t)b * N1;
+  double acc = 0;
+  for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
+    const double2 v = *reinterpret_cast<const double2*>(sb + e);
+    *reinterpret_cast<double2*>(db + e) = v;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[((int64_t)b * chunks + c) * MAXV] = t;
+}
+
 // t = sum_c partial[b][c][i]; with the Krylov scale s = sigma[b][i] (1 for
 // i >= nscaled or sigma == null): h[b][i] = t s and coef[b][i] = t s^2.
 __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partial, int nv, int chunks,
@@ -362,17 +382,17 @@ __global__ __launch_bounds__(NT) void k_update_t(const double* __restrict__ V, i
   if (threadIdx.x == 0) out[nv] = t;
 }
 
-// x[b] += sum_i y[b][i] Z_i[b]
+// x[b] += sum_i y[b][i] Z_i[b]  (x[b] = ... when overwrite: x is not read)
 template <typename Tz>
 __global__ __launch_bounds__(NT) void k_xupd(const Tz* __restrict__ Z, int64_t zstride, int nz,
                                              const double* __restrict__ yc, int ldy,
-                                             double* __restrict__ x, int64_t N1) {
+                                             double* __restrict__ x, int64_t N1, int overwrite) {
   const int b = blockIdx.y;
   double cf[MAXV];
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) cf[i] = (i < nz) ? yc[b * ldy + i] : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < N1; e += (int64_t)gridDim.x * NT) {
-    double v = x[(int64_t)b * N1 + e];
+    double v = overwrite ? 0.0 : x[(int64_t)b * N1 + e];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
       if (i < nz) v += cf[i] * (double)Z[i * zstride + (int64_t)b * N1 + e];
@@ -480,12 +500,17 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 }
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
-              const double* y, double* x, hipStream_t s) {
+              const double* y, double* x, bool overwrite, hipStream_t s) {
   dim3 grid(grid_for(pl.g.N1), pl.g.B);
   if (z_is_f32)
-    k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1);
+    k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
   else
-    k_xupd<double><<<grid, NT, 0, s>>>((const double*)Z, zstride, nz, y, MAXV, x, pl.g.N1);
+    k_xupd<double><<<grid, NT, 0, s>>>((const double*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
+}
+
+void copy_sq(const Plan& pl, const double* src, double* dst, double* partial, hipStream_t s) {
+  int chunks = dot_chunks(pl);
+  k_copy_sq<<<dim3(chunks, pl.g.B), NT, 0, s>>>(src, dst, partial, pl.g.N1, chunks);
 }
 
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s) {

@@ -171,7 +171,7 @@ __device__ __forceinline__ double2 load_pair(const double* __restrict__ row, int
 template <typename T, int TX>
 __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x, T* __restrict__ spec,
                                                    const double* __restrict__ gam,
-                                                   const double* __restrict__ bscale,
+                                                   const double* __restrict__ bscale, int bstride,
                                                    const typename V2<T>::t* __restrict__ tw, int Nt,
                                                    int logNt, int S, int sx, int sy, int reverse,
                                                    int gam_lds) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NT, 2) void k_fft_fwd(const double* __restrict__ x,
   const int b = bp.y;
   const int s0 = bp.x * TX;
   const double* xb = x + (int64_t)b * Nt * S;
-  const double sc = bscale ? bscale[b] : 1.0;
+  const double sc = bscale ? bscale[(int64_t)b * bstride] : 1.0;
   const bool vec = (S & 1) == 0;
   double* smg = reinterpret_cast<double*>(smtw + (Nt >> 1));   // Gamma
   // 1. stage: lane j of a row reads real columns (2j, 2j+1) with one 16-byte
@@ -415,7 +415,7 @@ __device__ __forceinline__ void fourstep_pass1(typename V2<T>::t (&c)[N1], typen
 template <typename T, int TX, int N1, int NTH = NT>
 __global__ __launch_bounds__(NTH, NTH / 128) void k_fft4_fwd(const double* __restrict__ x, T* __restrict__ spec,
                                                     const double* __restrict__ gam,
-                                                    const double* __restrict__ bscale,
+                                                    const double* __restrict__ bscale, int bstride,
                                                     const typename V2<T>::t* __restrict__ tw, int Nt,
                                                     int S, int sx, int sy, int reverse, int gam_lds,
                                                     int tw_lds) {
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(NTH, NTH / 128) void k_fft4_fwd(const double* __res
   const BlockPos bp = xcd_block();
   const int b = bp.y, s0 = bp.x * TX;
   const double* xb = x + (int64_t)b * Nt * S;
-  const double sc = bscale ? bscale[b] : 1.0;
+  const double sc = bscale ? bscale[(int64_t)b * bstride] : 1.0;
   const bool vec = (S & 1) == 0;
   const int j = threadIdx.x % NCOL, r = threadIdx.x / NCOL;
   const int s = s0 + 2 * j;
@@ -647,7 +647,7 @@ FftShape choose_shape(const Plan& pl) {
 }
 
 template <typename T>
-void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, int reverse,
+void launch_fwd(const Plan& pl, const double* x, const double* bscale, int bstride, T* spec, int reverse,
                 hipStream_t s, const typename V2<T>::t* tw) {
   const Geom& g = pl.g;
   FftShape sh = choose_shape(pl);
@@ -659,7 +659,7 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
   if (sh.TX == W && sh.n1 == N && sh.nth == H) {                                           \
     hipFuncSetAttribute((const void*)k_fft4_fwd<T, W, N, H>,                               \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
-    k_fft4_fwd<T, W, N, H><<<grid, H, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt,    \
+    k_fft4_fwd<T, W, N, H><<<grid, H, sh.lds, s>>>(x, spec, pl.d_gam, bscale, bstride, tw, g.nt, \
                                                    (int)g.S, g.sx, g.sy, reverse,          \
                                                    sh.gam_lds, sh.tw_lds);                 \
     return;                                                                                \
@@ -678,7 +678,7 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, T* spec, 
   case W:                                                                                  \
     hipFuncSetAttribute((const void*)k_fft_fwd<T, W>,                                      \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
-    k_fft_fwd<T, W><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, tw, g.nt, logNt,   \
+    k_fft_fwd<T, W><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, bstride, tw, g.nt, logNt, \
                                              (int)g.S, g.sx, g.sy, reverse, sh.gam_lds);   \
     break;
   switch (sh.TX) {
@@ -734,12 +734,12 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
 
 }  // namespace
 
-void fft_time_forward(const Plan& pl, const double* x, const double* bscale, void* spec,
+void fft_time_forward(const Plan& pl, const double* x, const double* bscale, int bstride, void* spec,
                       int reverse, hipStream_t s) {
   if (pl.prec == Prec::F64)
-    launch_fwd<double>(pl, x, bscale, (double*)spec, reverse, s, pl.d_tw64);
+    launch_fwd<double>(pl, x, bscale, bstride, (double*)spec, reverse, s, pl.d_tw64);
   else
-    launch_fwd<float>(pl, x, bscale, (float*)spec, reverse, s, pl.d_tw32);
+    launch_fwd<float>(pl, x, bscale, bstride, (float*)spec, reverse, s, pl.d_tw32);
 }
 
 void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, int accumulate,

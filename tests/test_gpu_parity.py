@@ -277,3 +277,46 @@ def test_gradient_autograd_matches_oracle():
     assert abs(J.item() - Jr) <= 1e-10 * abs(Jr)
     assert rel_err(U0g.grad.cpu().numpy().ravel(), gU0r) < 1e-9
     assert rel_err(fg.grad.cpu().numpy().reshape(prob.nt + 1, -1), gfr) < 1e-9
+
+
+def test_initial_guess_and_restarts():
+    """A warm start (use_x0) and a restart length that forces several cycles
+    both reach the oracle's solution; the first cycle from a zero guess
+    starts from V_0 = b without writing u until its first update."""
+    announce("initial guess and restarts")
+    torch, pd, prob = make(CASES["2d-tr-schur"], "fp32", restart=2)
+    b = np.random.default_rng(11).standard_normal((prob.nt, prob.nspace))
+    bg = to_gpu(torch, b, pd.shape)
+    ref = o_solve.sequential(prob, b)
+    u, res = pd.solve(bg, rtol=1e-10, max_iter=60, restart=2)
+    assert res.converged
+    assert rel_err(u.cpu().numpy().reshape(prob.nt, -1), ref) < 1e-8
+    # warm start from a perturbed solution: converges, and to the same answer
+    x0 = u + 1e-3 * torch.randn_like(u)
+    u2, res2 = pd.solve(bg, rtol=1e-10, max_iter=60, restart=2, x0=x0)
+    assert res2.converged
+    assert rel_err(u2.cpu().numpy().reshape(prob.nt, -1), ref) < 1e-8
+    # warm start from the solution itself: no iteration needed
+    u3, res3 = pd.solve(bg, rtol=1e-8, max_iter=60, restart=2, x0=u)
+    assert res3.converged and res3.iters == 0
+
+
+def test_stage_timing_selection():
+    announce("stage timing selection")
+    torch, pd, prob = make(CASES["2d-tr-schur"], "fp32")
+    r = torch.randn(pd.shape, dtype=torch.float64, device="cuda")
+    pd.set_timing(True, stages=["fft_fwd", "line_solve"])
+    pd.stage_times(reset=True)
+    pd.apply_precond(r)
+    st = pd.stage_times(reset=True)
+    assert st["fft_fwd"][1] == 1 and st["line_solve"][1] == 1
+    assert all(v[1] == 0 for k, v in st.items() if k not in ("fft_fwd", "line_solve"))
+    pd.set_timing(True)
+    pd.apply_precond(r)
+    st = pd.stage_times(reset=True)
+    assert all(st[k][1] == 1 for k in ("fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv"))
+    pd.set_timing(False)
+    pd.apply_precond(r)
+    assert all(v[1] == 0 for v in pd.stage_times(reset=True).values())
+    # a selector with bits past the last stage is rejected
+    assert pd.lib.paradiag_set_timing(pd.plan, 1 << 12) == -1
