@@ -10,12 +10,12 @@ x-transform) is timed next to the plain float64 one on the same problem;
 
 The JSON line also carries the roofline of the dominant kernel (algorithmic
 bytes or flops per launch over the average launch time, both measured by the
-library with HIP events on the solve's stream during the timed steps; the
-dominant stage is picked by an untimed solve, and only it records events
-in the timed region, since every event pair costs a few microseconds of
-stream time) and a CPU baseline: the float64 oracle's sequential time stepper
-on the same problem, timed on the host.  The per-stage breakdown comes from
-one extra solve before the timed region with every stage timed.
+library with HIP events on the solve's stream during the timed steps) and a
+CPU baseline: the float64 oracle's sequential time stepper on the same
+problem, timed on the host.  One extra solve before the timed region, with
+every stage timed, gives the per-stage breakdown and picks the dominant
+stage; inside the timed region only that stage records events, since every
+event pair costs a few microseconds of stream time.
 """
 
 from __future__ import annotations
