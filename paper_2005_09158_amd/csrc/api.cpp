@@ -212,10 +212,16 @@ size_t tables_bytes(const Plan& pl) {
   return b;
 }
 
+// partial-sum slots per right-hand side: the Krylov kernels' chunks or the
+// matvec's workgroups, whichever is more
+static size_t partial_chunks(const Plan& pl) {
+  return (size_t)std::max(2048, matvec_chunks(pl));
+}
+
 size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o) {
   if (!o) return 0;
   const Geom& g = pl.g;
-  size_t small = align_up(sizeof(double) * g.B * (size_t)2048 * MAXV) + 8 * align_up(sizeof(double) * g.B * MAXV);
+  size_t small = align_up(sizeof(double) * g.B * partial_chunks(pl) * MAXV) + 8 * align_up(sizeof(double) * g.B * MAXV);
   size_t zb = (pl.prec == Prec::F64) ? 8 : 4;
   if (o->mode == PD_MODE_FGMRES) {
     int m = std::max(1, std::min(o->restart, 32));
@@ -336,7 +342,7 @@ struct Small {
 Small carve_small(Plan& pl, char*& p) {
   const Geom& g = pl.g;
   Small sm;
-  sm.partial = (double*)p; p += align_up(sizeof(double) * g.B * (size_t)2048 * MAXV);
+  sm.partial = (double*)p; p += align_up(sizeof(double) * g.B * partial_chunks(pl) * MAXV);
   double** slots[] = {&sm.h1, &sm.c1, &sm.h2, &sm.c2, &sm.sigma, &sm.y, &sm.nrm};
   for (double** q : slots) { *q = (double*)p; p += align_up(sizeof(double) * g.B * MAXV); }
   p += align_up(sizeof(double) * g.B * MAXV);
@@ -563,17 +569,26 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a) and
       // read from the device copy of the scales, entry i * MAXV + j)
       apply_prec(pl, variant, Vj(j), sm.sigma + j, MAXV, Zj(j), zf32, 0, s);
-      apply_A(pl, variant, Zj(j), zf32, nullptr, Vj(j + 1), s);
       {
         double* w = Vj(j + 1);
-        // classical Gram-Schmidt, two passes; the second pass's dots come from the
-        // first pass's update kernel, the final norm by Pythagoras.  The second
+        // w = A z_j with the first pass's dots V_q . w (q <= j) from the same kernel
+        {
+          const double n = (double)g.NA;
+          Timed t(pl, PD_STAGE_MATVEC, s, n * ((zf32 ? 4.0 : 8.0) + 8.0 + 8.0 * (j + 1)),
+                  n * ((pl.L == 3 ? 22.0 : 18.0) + 2.0 * (j + 1)));
+          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial);
+        }
+        // classical Gram-Schmidt, two passes; the first pass's dots come from the
+        // matvec kernel, the second pass's from the first pass's update kernel,
+        // the final norm by Pythagoras.  The second
         // update is applied only when some live right-hand side keeps a
         // component along the basis above kReorthTol of its norm after the
         // first pass (selective reorthogonalisation): otherwise the vector is
         // already orthogonal to that accuracy and is kept as it is.
-        timed_dot(pl, V, vs, j + 1, w, sm.partial, s);
-        timed_reduce(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s);
+        {
+          Timed t(pl, PD_STAGE_OTHER, s);
+          reduce_partials(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl));
+        }
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
         hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);

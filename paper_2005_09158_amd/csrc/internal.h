@@ -144,8 +144,13 @@ void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu
 // all-at-once operator
+// y = A u (or b - A u).  With nv > 0 also the partial dots of y with the
+// vectors Vk + i vstride (i < nv), one per workgroup (matvec_chunks per
+// right-hand side, layout as multi_dot's partial sums).
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
-            double* y, int transpose, hipStream_t s);
+            double* y, int transpose, hipStream_t s, const double* Vk = nullptr,
+            int64_t vstride = 0, int nv = 0, double* partial = nullptr);
+int matvec_chunks(const Plan& pl);
 void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,
                hipStream_t s);
 void rhs_transpose(const Plan& pl, const double* lam, double* gU0, double* gu1, double* gf,
@@ -157,8 +162,9 @@ void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const d
                double* partial, hipStream_t s);
 // h[b][i] = t s, coef[b][i] = t s^2 with t the reduced dot and s = sigma[b][i]
 // for i < nscaled (else 1): dots against unnormalised Krylov vectors.
+// chunks: partial sums per right-hand side (<= 0: dot_chunks).
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
-                     int nscaled, double* h, double* coef, hipStream_t s);
+                     int nscaled, double* h, double* coef, hipStream_t s, int chunks = 0);
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
                 double* w, double* partial, int want_dots, hipStream_t s);
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,

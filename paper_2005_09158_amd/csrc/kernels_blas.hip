@@ -19,6 +19,20 @@ namespace pd {
 namespace {
 
 constexpr int NT = 256;
+constexpr int MAXV = 33;  // vectors per multi-dot (restart <= 32)
+
+// Sum over the workgroup, valid in thread 0: wave reduction, then across the
+// 4 waves in a fixed order.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
+  return t;
+}
 
 struct Stencil {
   double xl, xu, yl, yu, d;  // K u = xl u[x-1] + xu u[x+1] + yl u[y-1] + yu u[y+1] + d u
@@ -90,8 +104,8 @@ __device__ __forceinline__ void march_step(const double (&u0)[V], const double (
                                            const double (&bv)[V], bool hasb, int L, double c10,
                                            double c11, double c12, double c20, double c21,
                                            double c22, double (&u1)[V], double (&k1)[V],
-                                           double (&u2)[V], double (&k2)[V], double* dst) {
-  double r[V];
+                                           double (&u2)[V], double (&k2)[V], double* dst,
+                                           double (&r)[V]) {
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     r[v] = c10 * u0[v] + c20 * k0[v] + c11 * u1[v] + c21 * k1[v];
@@ -110,15 +124,26 @@ __device__ __forceinline__ void march_step(const double (&u0)[V], const double (
 // dir = +1: y = A u ;  dir = -1: y = A^T u (stencil already transposed by the
 // caller).  V = 4: four consecutive points per thread with 16-byte row loads
 // (nx % 4 == 0), which keeps four times the bytes in flight per load.
-template <typename Tin, int V>
+// NV != 0: also the dots of the result with the Krylov vectors V_i (i < nv;
+// NV > 0 fixed, NV < 0 any nv <= MAXV), one partial sum per workgroup in
+// partial[b][chunk][i], chunk = the workgroup's (x, time chunk) index --
+// the first Gram-Schmidt pass without a second read of the result.
+template <typename Tin, int V, int NV>
 __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const double* __restrict__ b,
                                                double* __restrict__ yv, int Nt, int nx, int ny, int L,
                                                double c10, double c11, double c12, double c20,
-                                               double c21, double c22, Stencil st, int chunk, int dir) {
+                                               double c21, double c22, Stencil st, int chunk, int dir,
+                                               const double* __restrict__ Vk, int64_t vstride, int nv,
+                                               double* __restrict__ partial) {
+  constexpr int NR = NV > 0 ? NV : (NV < 0 ? MAXV : 1);
+  __shared__ double red[4];
   const int S = nx * ny;
   const BlockPos bp = xcd_block();   // neighbouring rows of the stencil on one L2
   const int s = (bp.x * NT + threadIdx.x) * V;
-  if (s >= S) return;
+  double acc[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) acc[i] = 0.0;
+  if (s < S) {
   const int x = s % nx, y = s / nx;
   const int64_t boff = (int64_t)bp.z * Nt * S;
   const Tin* ub = u + boff;
@@ -154,9 +179,44 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
       ldv<double, V>(bb + offA, bA);
       ldv<double, V>(bb + offB, bB);
     }
-    march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA);
-    if (i + 1 < cnt)
-      march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB);
+    double rA[V], rB[V];
+    march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA, rA);
+    if constexpr (NV != 0) {
+      const double* Vb = Vk + boff;
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (NV > 0 || q < nv) {
+          double vq[V];
+          ldv<double, V>(Vb + q * vstride + offA, vq);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[q] += vq[v] * rA[v];
+        }
+    }
+    if (i + 1 < cnt) {
+      march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB, rB);
+      if constexpr (NV != 0) {
+        const double* Vb = Vk + boff;
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+          if (NV > 0 || q < nv) {
+            double vq[V];
+            ldv<double, V>(Vb + q * vstride + offB, vq);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[q] += vq[v] * rB[v];
+          }
+      }
+    }
+  }
+  }  // s < S
+  if constexpr (NV != 0) {
+    const int chunks = gridDim.x * gridDim.y;
+    double* out = partial + ((int64_t)bp.z * chunks + bp.x + (int64_t)gridDim.x * bp.y) * MAXV;
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (NV > 0 || q < nv) {   // nv is uniform: every thread reaches the barriers
+        const double t = block_sum(acc[q], red);
+        if (threadIdx.x == 0) out[q] = t;
+      }
   }
 }
 
@@ -239,20 +299,6 @@ __global__ __launch_bounds__(NT) void k_rhs_t(const double* __restrict__ lam, do
   }
 }
 
-// ----------------------------------------------------------- Krylov helpers
-constexpr int MAXV = 33;  // vectors per multi-dot (restart <= 32)
-
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  // wave reduction then across the 4 waves (fixed order)
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0;
-  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
-  return t;
-}
 
 // Multi-dot and update kernels, templated on the number of Krylov vectors
 // (NV <= 8; larger counts use the generic predicated form).  Each thread
@@ -417,25 +463,48 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
-            double* y, int transpose, hipStream_t s) {
+static dim3 matvec_grid(const Plan& pl, int& V, int& chunk) {
   const Geom& g = pl.g;
-  const int chunk = 16;
-  const int V = (g.nx % 4) == 0 ? 4 : 1;
-  dim3 grid((unsigned)((g.S / V + NT - 1) / NT), (g.nt + chunk - 1) / chunk, g.B);
+  chunk = 16;
+  V = (g.nx % 4) == 0 ? 4 : 1;
+  return dim3((unsigned)((g.S / V + NT - 1) / NT), (g.nt + chunk - 1) / chunk, g.B);
+}
+
+int matvec_chunks(const Plan& pl) {
+  int V, chunk;
+  const dim3 gr = matvec_grid(pl, V, chunk);
+  return (int)(gr.x * gr.y);
+}
+
+void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
+            double* y, int transpose, hipStream_t s, const double* Vk, int64_t vstride, int nv,
+            double* partial) {
+  int V, chunk;
+  const dim3 grid = matvec_grid(pl, V, chunk);
   Stencil st = stencil_of(op);
   int dir = transpose ? -1 : 1;
-#define PD_MV(TIN, VV)                                                                            \
-  k_matvec<TIN, VV><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0],    \
-                                        pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,     \
-                                        chunk, dir)
-  if (u_is_f32) {
-    if (V == 4) PD_MV(float, 4);
-    else PD_MV(float, 1);
-  } else {
-    if (V == 4) PD_MV(double, 4);
-    else PD_MV(double, 1);
+  const Geom& g = pl.g;
+#define PD_MV(TIN, VV, K)                                                                         \
+  k_matvec<TIN, VV, K><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0], \
+                                           pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \
+                                           chunk, dir, Vk, vstride, nv, partial)
+#define PD_MV_NV(TIN, VV)                                                                         \
+  switch (nv) {                                                                                   \
+    case 0: PD_MV(TIN, VV, 0); break;                                                             \
+    case 1: PD_MV(TIN, VV, 1); break;                                                             \
+    case 2: PD_MV(TIN, VV, 2); break;                                                             \
+    case 3: PD_MV(TIN, VV, 3); break;                                                             \
+    case 4: PD_MV(TIN, VV, 4); break;                                                             \
+    default: PD_MV(TIN, VV, -1); break;                                                           \
   }
+  if (u_is_f32) {
+    if (V == 4) { PD_MV_NV(float, 4) }
+    else { PD_MV_NV(float, 1) }
+  } else {
+    if (V == 4) { PD_MV_NV(double, 4) }
+    else { PD_MV_NV(double, 1) }
+  }
+#undef PD_MV_NV
 #undef PD_MV
 }
 
@@ -476,8 +545,8 @@ void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const d
 }
 
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
-                     int nscaled, double* h, double* coef, hipStream_t s) {
-  int chunks = dot_chunks(pl);
+                     int nscaled, double* h, double* coef, hipStream_t s, int chunks) {
+  if (chunks <= 0) chunks = dot_chunks(pl);
   k_reduce<<<dim3(nv, pl.g.B), NT, 0, s>>>(partial, nv, chunks, sigma, nscaled, h, coef, MAXV);
 }
 
