@@ -96,20 +96,31 @@ def make_inputs(cfg, torch, pd):
 
 def run_precision(cfg, prec, args, torch):
     from paper_2005_09158_amd import ParaDiag
-    pd = ParaDiag(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, scheme=cfg.scheme, T=cfg.T,
-                  nu=cfg.nu, ax=cfg.ax, ay=cfg.ay, alpha=cfg.alpha, batch=cfg.batch, prec=prec,
-                  restart=args.restart)
+    # the FGMRES workspace holds restart+1 float64 and restart preconditioned
+    # vectors: a shorter restart where the requested one does not fit in HBM
+    restart, pd = args.restart, None
+    while pd is None:
+        try:
+            pd = ParaDiag(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, scheme=cfg.scheme, T=cfg.T,
+                          nu=cfg.nu, ax=cfg.ax, ay=cfg.ay, alpha=cfg.alpha, batch=cfg.batch,
+                          prec=prec, restart=restart)
+        except torch.OutOfMemoryError:
+            torch.cuda.empty_cache()
+            if restart <= 2:
+                raise
+            restart -= 1
+            print(f"[bench] {prec}: workspace does not fit, restart {restart}", file=sys.stderr, flush=True)
     U0, u1, f = make_inputs(cfg, torch, pd)
     b = pd.build_rhs(U0, u1, f)
     del f
     u = torch.empty_like(b)
     for _ in range(args.warmup):
-        pd.solve(b, u, rtol=cfg.rtol, max_iter=200)
+        pd.solve(b, u, rtol=cfg.rtol, max_iter=200, restart=restart)
     # one solve with every stage timed, outside the timed region: the per-stage
     # breakdown, and the dominant stage
     pd.set_timing(True)
     pd.stage_times(reset=True)
-    pd.solve(b, u, rtol=cfg.rtol, max_iter=200)
+    pd.solve(b, u, rtol=cfg.rtol, max_iter=200, restart=restart)
     stages = pd.stage_times(reset=True)
     dominant = max(stages, key=lambda k: stages[k][0])
     # timed region: only the dominant stage records events (they cost time)
@@ -119,14 +130,14 @@ def run_precision(cfg, prec, args, torch):
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
-        _, res = pd.solve(b, u, rtol=cfg.rtol, max_iter=200)
+        _, res = pd.solve(b, u, rtol=cfg.rtol, max_iter=200, restart=restart)
         results.append(res)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timed = pd.stage_times(reset=True)
     pd.set_timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
-    out = dict(prec=prec, ms_per_step=ms, iters=[r.iters for r in results],
+    out = dict(prec=prec, ms_per_step=ms, restart=restart, iters=[r.iters for r in results],
                rel_resid=max(r.rel_resid for r in results),
                converged=all(r.converged for r in results), stages=stages, dominant=dominant,
                dominant_timed=timed[dominant])
@@ -253,15 +264,15 @@ def main():
     torch.cuda.set_device(0)
     print(f"[bench] workload {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nt} batch {cfg.batch} "
           f"scheme {cfg.scheme} alpha {cfg.alpha}", file=sys.stderr, flush=True)
-    mixed, pdm, _ = run_precision(cfg, args.mixed, args, torch)
+    mixed, pdm, um = run_precision(cfg, args.mixed, args, torch)
     print(f"[bench] {args.mixed}: {mixed['ms_per_step']:.3f} ms/solve iters {mixed['iters']} "
           f"resid {mixed['rel_resid']:.2e}", file=sys.stderr, flush=True)
-    del pdm
+    del pdm, um
     torch.cuda.empty_cache()
     fp64 = None
     if not args.skip_fp64:
-        fp64, pd64, _ = run_precision(cfg, "fp64", args, torch)
-        del pd64
+        fp64, pd64, u64 = run_precision(cfg, "fp64", args, torch)
+        del pd64, u64
         torch.cuda.empty_cache()
         print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/solve iters {fp64['iters']} "
               f"resid {fp64['rel_resid']:.2e}", file=sys.stderr, flush=True)
