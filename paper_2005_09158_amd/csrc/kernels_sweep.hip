@@ -290,7 +290,11 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
       const int e = lane + 64 * u;
       if (e < total) {
         const int kv = e % NV, comp = (e / NV) & 1, y = y0 + e / (2 * NV);
-        v[u] = *reinterpret_cast<const V*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV);
+        // read once before the block is solved: non-temporal (see load_inv)
+        typedef T NV4 __attribute__((ext_vector_type(MV)));
+        const NV4 t = __builtin_nontemporal_load(
+            reinterpret_cast<const NV4*>(slice + (int64_t)y * 2 * sx + comp * sx + k0 + kv * MV));
+        v[u] = __builtin_bit_cast(V, t);
       }
     }
 #pragma unroll
@@ -408,11 +412,30 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       const Cx<T>* tbc = reinterpret_cast<const Cx<T>*>(tbs + cur * 2 * NB * NB);
       const Cx<T>* tnc = reinterpret_cast<const Cx<T>*>(tns + cur * 2 * NB * NB);
       const T* lun = lu + (int64_t)n * sx * sy * 2;
+      // inverse pivots: read once, so loaded non-temporally (they should not
+      // push the solved lines, which the coupling product re-reads, out of
+      // the last-level cache)
       auto load_inv = [&](int q, Cx<T> (&iv)[R]) {
         const T* src = lun + ((int64_t)(k0 + q) * sy + p * R) * 2;
+        if constexpr (sizeof(T) == 4 && R % 2 == 0) {
+          typedef float f4v __attribute__((ext_vector_type(4)));
+          const bool full = active && p * R + R <= sy;
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-          iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
+          for (int h = 0; h < R / 2; ++h) {
+            f4v v = {1.f, 0.f, 1.f, 0.f};
+            if (full) v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(src) + h);
+            iv[2 * h] = Cx<T>{v.x, v.y};
+            iv[2 * h + 1] = Cx<T>{v.z, v.w};
+          }
+          if (!full)
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+              iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
+        } else {
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
+        }
       };
       Cx<T> d[NB][R];
 #pragma unroll
