@@ -85,10 +85,31 @@ def test_schur_sweep_shapes(nx, ny, prec):
     assert err < PREC_TOL[prec]
 
 
+# Line-solver shapes (sine basis): lines of 256 .. 512 rows take 8 rows per
+# lane (32 or 64 lanes per line), a ragged length pads the last lane, and an
+# x-size that is not a multiple of 4 takes the element-wise tile copies.
+LINE_SHAPES = [(8, 256), (6, 300), (4, 512), (5, 129)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny", LINE_SHAPES)
+def test_line_solver_shapes(nx, ny, prec):
+    announce(f"line shape {nx}x{ny} {prec}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nt=8, scheme="lf", T=1.0, nu=1.0, alpha=1e-2)
+    torch, pd, prob = make(cfg, prec)
+    r = np.random.default_rng(13).standard_normal((prob.nt, prob.nspace))
+    z_ref = o_prec.three_steps(prob, r)
+    z = pd.apply_precond(to_gpu(torch, r, pd.shape))
+    torch.cuda.synchronize()
+    err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
+    print(f"  rel err {err:.3e}")
+    assert err < PREC_TOL[prec]
+
+
 # Time-FFT shapes: on a 16 x 8 grid (sine basis) these Nt select the
 # four-step kernels with pencil lengths 4 .. 32 and tiles of 32, 16 and 8
-# columns (Nt = 2048 reads its twiddles through the caches), and the
-# Stockham kernel below them.
+# columns (Nt = 2048 in float32, and Nt = 512 and 1024 in float64, take the
+# 512-thread workgroups), and the Stockham kernel below them.
 FFT_NT = {"fp32": [16, 64, 128, 256, 512, 2048], "fp64": [16, 64, 256, 512, 1024]}
 
 
