@@ -19,7 +19,11 @@
 // between the read barrier and the write barrier.  The pair is then split
 // into the two half spectra, X_a = (Z_k + conj Z_{Nt-k})/2 and
 // X_b = (Z_k - conj Z_{Nt-k})/(2i), and written row-planar.  The inverse runs
-// the same steps backwards, using ifft(Z) = conj(fft(conj Z))/Nt.
+// the same steps backwards, using ifft(Z) = conj(fft(conj Z))/Nt.  Where Nt
+// splits as N1 x (threads per column), the four-step kernels further down
+// transform each thread's loaded pencil in registers first and leave only the
+// remaining passes to LDS.  Workgroups are renumbered so that each XCD owns a
+// contiguous range of tiles (xcd_block): neighbouring tiles share cache lines.
 
 #include "internal.h"
 
@@ -598,9 +602,11 @@ inline size_t fourstep_cols(int tx, int nt, size_t csize, int nth = NT) {
 // n1 > 0: four-step kernels; lds_inv: bytes of the inverse (no Gamma table)
 struct FftShape { int TX; size_t lds; bool gam_lds; int n1; bool tw_lds; size_t lds_inv; int nth; };
 
-// Widest tile (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex
-// columns of Nt+1 entries plus the twiddle table -- lets two workgroups share
-// a CU, and whose FFT pass fits the per-thread register budget.
+// Tile shape: the four-step form where an instantiated (TX, N1, threads)
+// fits (see the preference order below), else the widest Stockham tile
+// (TX <= 32 spatial unknowns) whose LDS image -- TX/2 complex columns of
+// Nt+1 entries plus half the twiddle table -- lets two workgroups share a
+// CU, and whose FFT pass fits the per-thread register budget.
 FftShape choose_shape(const Plan& pl) {
   const Geom& g = pl.g;
   const bool f64 = pl.prec == Prec::F64;
