@@ -24,6 +24,8 @@
 // staged global -> LDS in batches of 8 loads per thread rather than
 // prefetched whole into registers.
 
+#include <type_traits>
+
 #include "tri_device.h"
 
 namespace pd {
@@ -192,14 +194,14 @@ __device__ __forceinline__ void mma_frag(const CouplingFrag<T, RB>& f, int part,
 // fragments of the next 16 modes loaded while the current ones multiply.
 template <typename T, int NB, int RB, bool VEC>
 __device__ __forceinline__ void coupling_far(const T* slice, const T* tre, const T* tim, int sx, int sy,
-                                             int k0n, int kend, int cw, int lr, int lk,
+                                             int k0n, int kend, int y0, int lr, int lk,
                                              typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
   constexpr int NCB = 2 * NB / 16;
   const int q = (NCB == 2) ? lr : (lr & 7);
   const int part = (NCB == 2) ? 0 : (lr >> 3);
   const T* trow = tre + (int64_t)(k0n + q) * sx;
   const T* irow = tim + (int64_t)(k0n + q) * sx;
-  const int r0 = cw * RB * 16 + lr;
+  const int r0 = y0 + lr;
   if (kend >= sx) return;
   CouplingFrag<T, RB> fa, fb;
   load_frag<T, RB, VEC>(fa, slice, trow, irow, sx, sy, kend + 4 * lk, true, r0);
@@ -336,7 +338,7 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
 constexpr int NCW = 3;
 constexpr int SWT = 64 * (NCW + 1);
 
-template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB>
+template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B>
 __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                      const T* __restrict__ tup, const T* __restrict__ lu,
                                                      double lo, double up, int F, int sx, int sy, int ldy) {
@@ -403,6 +405,53 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
     __syncthreads();   // block kb+1 in global memory; its LDS buffer is free
     const int k0n = k0 - NB;   // next block (always full) when kb > 0
+    // Rows [y0, y1) of block kb-1: staged into the LDS buffer, coupled to every
+    // mode beyond block kb (read from global memory), and lambda2 times the
+    // coupling subtracted.  One wave; it touches only its own rows.
+    auto prep_rows = [&](auto rbx, int y0, int y1, int lane, int lr, int lk) {
+      constexpr int RBX = decltype(rbx)::value;
+      tile_rows_load<T, NB, RBX * 16, VEC>(slice, nre, nim, k0n, sx, y0, y1, ldy, R, lane);
+      typename MF::acc_t acc[RBX][NCB];
+#pragma unroll
+      for (int i = 0; i < RBX; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+      coupling_far<T, NB, RBX, VEC>(slice, tre, tim, sx, sy, k0n, kend, y0, lr, lk, acc);
+      // tile -= lambda2 C: all LDS reads first, then all writes (one
+      // read-modify-write at a time would expose the LDS latency per value)
+      const bool col_ok = NCB == 2 || lr < 8;
+      T tr_[RBX][4], ti_[RBX][4];
+#pragma unroll
+      for (int i = 0; i < RBX; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = y0 + i * 16 + MF::row(lk, v);
+          const int idx = lidx(lr, y, ldy, R);
+          tr_[i][v] = (y < sy && col_ok) ? nre[idx] : (T)0;
+          ti_[i][v] = (y < sy && col_ok) ? nim[idx] : (T)0;
+        }
+#pragma unroll
+      for (int i = 0; i < RBX; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int y = y0 + i * 16 + MF::row(lk, v);
+          T cr, ci;
+          if constexpr (NCB == 2) {
+            cr = acc[i][0][v];
+            ci = acc[i][1][v];
+          } else {
+            cr = acc[i][0][v];
+            ci = dpp_mov<0x108>(acc[i][0][v]);   // imaginary part from lane lr + 8 (row_shl:8)
+          }
+          if (y < sy && col_ok) {
+            const int idx = lidx(lr, y, ldy, R);
+            nre[idx] = tr_[i][v] - (l2r * cr - l2i * ci);
+            nim[idx] = ti_[i][v] - (l2r * ci + l2i * cr);
+          }
+        }
+    };
     if (wave == 0) {
       // ---- block kb: near coupling, then its lines in order ------------
       const bool active = lane < P;
@@ -492,12 +541,16 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
             cim[idx] = d[q][i].y;
           }
         }
+      // the first W0B row blocks of block kb-1's preparation: wave 0 finishes
+      // its lines before the coupling waves finish theirs, so it takes a share
+      if constexpr (W0B > 0)
+        if (kb > 0) prep_rows(std::integral_constant<int, W0B>{}, 0, min(sy, W0B * 16), lane, lr, lk);
     } else if (kb > 0) {
       // ---- block kb-1: tile, coupling to the modes beyond block kb -----
       // Wave cw stages exactly the rows its accumulators cover, so its
       // subtraction depends only on its own LDS writes (in program order).
       const int ct = tid - 64, cw = wave - 1;
-      const int y0 = cw * RB * 16, y1 = min(sy, y0 + RB * 16);
+      const int y0 = (W0B + cw * RB) * 16, y1 = min(sy, y0 + RB * 16);
       // coefficients of block kb-1 (inside it; towards block kb): loads
       // issued now, their latency hidden behind the tile and the products
       static_assert(NB * NB <= SWT - 64, "one coefficient per thread");
@@ -514,47 +567,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
           cni = tim[row + k0 + qb];
         }
       }
-      tile_rows_load<T, NB, RB * 16, VEC>(slice, nre, nim, k0n, sx, y0, y1, ldy, R, lane);
-      typename MF::acc_t acc[RB][NCB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int j = 0; j < NCB; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
-      coupling_far<T, NB, RB, VEC>(slice, tre, tim, sx, sy, k0n, kend, cw, lr, lk, acc);
-      // tile -= lambda2 C: all LDS reads first, then all writes (one
-      // read-modify-write at a time would expose the LDS latency per value)
-      const bool col_ok = NCB == 2 || lr < 8;
-      T tr_[RB][4], ti_[RB][4];
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int y = y0 + i * 16 + MF::row(lk, v);
-          const int idx = lidx(lr, y, ldy, R);
-          tr_[i][v] = (y < sy && col_ok) ? nre[idx] : (T)0;
-          ti_[i][v] = (y < sy && col_ok) ? nim[idx] : (T)0;
-        }
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int y = y0 + i * 16 + MF::row(lk, v);
-          T cr, ci;
-          if constexpr (NCB == 2) {
-            cr = acc[i][0][v];
-            ci = acc[i][1][v];
-          } else {
-            cr = acc[i][0][v];
-            ci = dpp_mov<0x108>(acc[i][0][v]);   // imaginary part from lane lr + 8 (row_shl:8)
-          }
-          if (y < sy && col_ok) {
-            const int idx = lidx(lr, y, ldy, R);
-            nre[idx] = tr_[i][v] - (l2r * cr - l2i * ci);
-            nim[idx] = ti_[i][v] - (l2r * ci + l2i * cr);
-          }
-        }
+      prep_rows(std::integral_constant<int, RB>{}, y0, y1, lane, lr, lk);
       if (ct < NB * NB) {
         T* bt = tbs + nxt * 2 * NB * NB;
         T* bn = tns + nxt * 2 * NB * NB;
@@ -856,7 +869,7 @@ size_t piped_lds(const SweepShape& sh) {
   return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64);
 }
 
-template <typename T, int R, int P, int NB, int RB>
+template <typename T, int R, int P, int NB, int RB, int W0B>
 void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, 16>(pl);
@@ -865,7 +878,8 @@ void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   // an odd number of slices, or more slices than CUs, then leaves no CU idle
   // while a last slice runs alone
   constexpr int MINB = (R == 4) ? 2 : 1;
-  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB> : k_schur_sweep<T, R, P, NB, RB, false, MINB>;
+  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B>
+                    : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B>;
   hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
                                        g.F, g.sx, g.sy, sh.ldy);
@@ -892,17 +906,18 @@ void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   using PC = PipedCfg<T>;
   SweepShape sh = sweep_shape<T, C::NB, C::BK>(pl);
   if constexpr (PC::NB8 > 0) {   // float32: pipelined kernel
-    // row blocks per coupling wave by line length: <= 64 rows: 2 (4 blocks),
-    // <= 128: 3 (8 blocks), <= 256: 6 (16 blocks), <= 512: 11 (32 blocks)
-#define PD_PIPED(RR, PP, BB, NBV)                                                         \
+    // row blocks of 16 rows: W0 for wave 0 (after its lines), RB per coupling
+    // wave, W0 + 3 RB >= rows / 16: <= 64 rows: 0 + 3 x 2, <= 128: 0 + 3 x 3,
+    // <= 256: 1 + 3 x 5, <= 512: 2 + 3 x 10
+#define PD_PIPED(RR, PP, BB, W0, NBV)                                                     \
   if (sh.R == RR && sh.P == PP) {                                                         \
-    launch_piped<T, RR, PP, NBV, BB>(pl, op, spec, s);                                    \
+    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s);                                \
     return;                                                                               \
   }
-    PD_PIPED(4, 1, 2, PC::NB4) PD_PIPED(4, 2, 2, PC::NB4) PD_PIPED(4, 4, 2, PC::NB4)
-    PD_PIPED(4, 8, 2, PC::NB4) PD_PIPED(4, 16, 2, PC::NB4) PD_PIPED(4, 32, 3, PC::NB4)
-    PD_PIPED(4, 64, 6, PC::NB4)
-    PD_PIPED(8, 64, 11, PC::NB8)
+    PD_PIPED(4, 1, 2, 0, PC::NB4) PD_PIPED(4, 2, 2, 0, PC::NB4) PD_PIPED(4, 4, 2, 0, PC::NB4)
+    PD_PIPED(4, 8, 2, 0, PC::NB4) PD_PIPED(4, 16, 2, 0, PC::NB4) PD_PIPED(4, 32, 3, 0, PC::NB4)
+    PD_PIPED(4, 64, 5, 1, PC::NB4)
+    PD_PIPED(8, 64, 10, 2, PC::NB8)
 #undef PD_PIPED
     return;
   }
