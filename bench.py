@@ -40,11 +40,11 @@ PEAK = {  # MI355X published peaks
 # bound of each stage of the library's accounting
 STAGE_BOUND = {"fft_fwd": "hbm", "fft_inv": "hbm", "line_solve": "hbm", "matvec": "hbm",
                "dot": "hbm", "update": "hbm", "other": "hbm", "xform_fwd": "mfma",
-               "xform_inv": "mfma", "line_pairs": "hbm"}
+               "xform_inv": "mfma"}
 
 STAGE_KERNEL = {"fft_fwd": "k_fft_fwd", "fft_inv": "k_fft_inv", "line_solve": "k_schur_sweep",
                 "matvec": "k_matvec", "dot": "k_mdot", "update": "k_update", "other": "k_reduce",
-                "xform_fwd": "k_gemm", "xform_inv": "k_gemm", "line_pairs": "k_schur_sweep"}
+                "xform_fwd": "k_gemm", "xform_inv": "k_gemm"}
 
 
 def parse():
@@ -122,9 +122,7 @@ def run_precision(cfg, prec, args, torch):
     pd.stage_times(reset=True)
     pd.solve(b, u, rtol=cfg.rtol, max_iter=200, restart=restart)
     stages = pd.stage_times(reset=True)
-    # line_pairs (the back-sweep's slice pairs on a second stream) runs beside
-    # line_solve and the inverse x-transform, off the critical path
-    dominant = max((k for k in stages if k != "line_pairs"), key=lambda k: stages[k][0])
+    dominant = max(stages, key=lambda k: stages[k][0])
     # timed region: only the dominant stage records events (they cost time)
     pd.set_timing(True, stages=[dominant])
     pd.stage_times(reset=True)
@@ -183,7 +181,7 @@ def roofline(run, cfg, traffic_file):
     name = run["dominant"]
     ms, cnt, by, fl = run["dominant_timed"]   # events of the timed region
     bound = STAGE_BOUND[name]
-    if name in ("line_solve", "line_pairs") and cfg.dim == 2 and cfg.ax != 0.0:
+    if name == "line_solve" and cfg.dim == 2 and cfg.ax != 0.0:
         bound = "mfma"  # Schur back-sweep: the coupling product runs on MFMA
     avg_s = ms / 1e3 / max(cnt, 1)
     if bound == "hbm":
@@ -192,8 +190,7 @@ def roofline(run, cfg, traffic_file):
     elif bound == "mfma":
         achieved = fl / max(cnt, 1) / avg_s / 1e12
         # the back-sweep's products run in the line precision (float32 in mixed modes)
-        key = (run["prec"] if name not in ("line_solve", "line_pairs")
-               else ("fp64" if run["prec"] == "fp64" else "fp32"))
+        key = run["prec"] if name != "line_solve" else ("fp64" if run["prec"] == "fp64" else "fp32")
         peak, unit = PEAK["mfma_TFs"][key], "TFLOP/s"
     else:
         achieved = fl / max(cnt, 1) / avg_s / 1e12

@@ -208,9 +208,7 @@ enum {
   PD_STAGE_DOT = 6,        /* Krylov multi-dot products */
   PD_STAGE_UPDATE = 7,     /* Krylov vector updates (fused with the next dots) */
   PD_STAGE_OTHER = 8,      /* reductions of partial sums, solution update, copies */
-  PD_STAGE_LINE_PAIRS = 9, /* Step-(b): back-sweep of the slices beyond one per CU, two per
-                              workgroup on a second stream, beside PD_STAGE_LINE_SOLVE */
-  PD_NUM_STAGES = 10
+  PD_NUM_STAGES = 9
 };
 paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable);
 paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,

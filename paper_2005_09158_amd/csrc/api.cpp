@@ -303,37 +303,7 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
   { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, bstride, pl.spec_a, variant, s); }
-  const int pairs = (pl.p.dim == 2 && pl.schur && pl.s2) ? schur_sweep_pairs(pl) : 0;
-  if (pl.p.dim == 2 && pairs > 0) {
-    // More slices than CUs by a few: the single slices [0, tA) run one per
-    // CU on the caller's stream, the last 2 * pairs slices two per workgroup
-    // on CUs of their own on the second stream, and each side's inverse
-    // x-transform starts as soon as its own slices are solved.
-    const Geom& g = pl.g;
-    const int W = g.F * g.B, tA = W - 2 * pairs;
-    const double fA = (double)tA / W, fB = 1.0 - fA;
-    { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
-    hipEventRecord(pl.ev_fork, s);
-    hipStreamWaitEvent(pl.s2, pl.ev_fork, 0);
-    {
-      Timed t(pl, PD_STAGE_LINE_PAIRS, pl.s2, 2 * sb * fB, sweep_flops(pl) * fB);
-      schur_sweep(pl, op, pl.spec_b, pl.s2, tA, 2 * pairs, true);
-    }
-    {
-      Timed t(pl, PD_STAGE_XFORM_INV, pl.s2, 2 * sb * fB, xform_flops(pl) * fB);
-      xform(pl, op, false, pl.spec_b, pl.spec_a, pl.s2, (int64_t)tA * g.sy, (int64_t)2 * pairs * g.sy);
-    }
-    hipEventRecord(pl.ev_join, pl.s2);
-    {
-      Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb * fA, sweep_flops(pl) * fA);
-      schur_sweep(pl, op, pl.spec_b, s, 0, tA, false);
-    }
-    {
-      Timed t(pl, PD_STAGE_XFORM_INV, s, 2 * sb * fA, xform_flops(pl) * fA);
-      xform(pl, op, false, pl.spec_b, pl.spec_a, s, 0, (int64_t)tA * g.sy);
-    }
-    hipStreamWaitEvent(s, pl.ev_join, 0);
-  } else if (pl.p.dim == 2) {
+  if (pl.p.dim == 2) {
     { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
     {
       Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, pl.schur ? sweep_flops(pl) : 0.0);
@@ -764,9 +734,6 @@ void paradiag_destroy(paradiag_plan plan) {
   for (auto& r : pl->timer.pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
   for (auto e : pl->timer.pool) hipEventDestroy(e);
   if (pl->pin) hipHostFree(pl->pin);
-  if (pl->s2) hipStreamDestroy(pl->s2);
-  if (pl->ev_fork) hipEventDestroy(pl->ev_fork);
-  if (pl->ev_join) hipEventDestroy(pl->ev_join);
   delete pl;
 }
 
@@ -795,14 +762,6 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
       pl->num_cu = ncu;
-  }
-  if (!pl->s2 && pl->schur) {
-    if (hipStreamCreateWithFlags(&pl->s2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
-      set_error("stream or event creation failed");
-      return PD_ERR_HIP;
-    }
   }
   char* p = (char*)workspace;
   auto take = [&](size_t n) { char* r = p; p += align_up(n); return r; };

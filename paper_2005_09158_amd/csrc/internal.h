@@ -119,10 +119,6 @@ struct Plan {
   // pinned host staging of the solvers' small transfers (Krylov scalars, norms)
   double* pin = nullptr;
   size_t pin_n = 0;
-  // second stream (default priority) for the back-sweep's slice pairs, and
-  // the events that fork it from and join it to the caller's stream
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 size_t spec_elem_bytes(Prec p);          // 8 (double) or 4 (float)
@@ -141,17 +137,10 @@ void fft_time_forward(const Plan& pl, const double* x, const double* bscale, int
 void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, int accumulate,
                       int reverse, hipStream_t s);
 // Step-(b) pieces
-// x-transform of complex rows row0 .. row0+nrows-1 (nrows < 0: to the end)
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
-           hipStream_t s, int64_t row0 = 0, int64_t nrows = -1);
+           hipStream_t s);
 void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
-// Schur back-sweep over slices t0 .. t0+count-1 (slice = rhs * F + frequency;
-// count < 0: to the end); dual: two slices per workgroup on CUs of their own.
-void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s, int t0 = 0,
-                 int count = -1, bool dual = false);
-// Slices beyond one per CU when they are few (0 otherwise): the last
-// 2 * schur_sweep_pairs slices then run as pairs beside the others.
-int schur_sweep_pairs(const Plan& pl);
+void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu
 // all-at-once operator

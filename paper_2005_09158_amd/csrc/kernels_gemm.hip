@@ -332,16 +332,10 @@ void launch_gemm_bf16(const float* A, const unsigned short* Bt, float* C, int64_
 }  // namespace
 
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
-           hipStream_t s, int64_t row0, int64_t nrows) {
+           hipStream_t s) {
   const Geom& g = pl.g;
   const void* Bt = forward ? op.g_fwd : op.g_inv;
-  // complex rows of length sx (each 2 sx reals: sx real parts, sx imaginary)
-  const int64_t all = (int64_t)g.B * g.F * g.sy;
-  int64_t rows = nrows < 0 ? all - row0 : nrows;
-  if (rows <= 0) return;
-  const size_t esz = pl.prec == Prec::F64 ? 8 : 4;
-  in = (const char*)in + (size_t)row0 * 2 * g.sx * esz;
-  out = (char*)out + (size_t)row0 * 2 * g.sx * esz;
+  int64_t rows = (int64_t)g.B * g.F * g.sy;   // complex rows of length sx
   int64_t M;
   int N, K;
   if (pl.schur) {

@@ -24,7 +24,6 @@
 // staged global -> LDS in batches of 8 loads per thread rather than
 // prefetched whole into registers.
 
-#include <algorithm>
 #include <type_traits>
 
 #include "tri_device.h"
@@ -339,21 +338,15 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
 constexpr int NCW = 3;
 constexpr int SWT = 64 * (NCW + 1);
 
-// SL slices per workgroup (1, or 2: two independent slices side by side in one
-// workgroup of 2 x SWT threads, each half with its own LDS region of
-// lds_slice bytes, sharing only the barriers).  Slice t0 + SL blockIdx.x + half.
-template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B, int SL>
-__global__ __launch_bounds__(SWT * SL, SL == 1 ? MINB : 1) void k_schur_sweep(
-    T* __restrict__ spec, const double2* __restrict__ lam, const T* __restrict__ tup,
-    const T* __restrict__ lu, double lo, double up, int F, int sx, int sy, int ldy, int t0,
-    int lds_slice) {
+template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B>
+__global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
+                                                     const T* __restrict__ tup, const T* __restrict__ lu,
+                                                     double lo, double up, int F, int sx, int sy, int ldy) {
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
   using MF = SweepMfma<T>;
   constexpr int NCB = 2 * NB / 16;
-  const int half = SL == 1 ? 0 : (int)(threadIdx.x / SWT);
-  const int tx = (int)threadIdx.x - half * SWT;   // thread index within the slice
   extern __shared__ __align__(16) unsigned char smraw[];
-  T* tiles = reinterpret_cast<T*>(smraw + (size_t)half * lds_slice);   // [2 buffers][re, im][NB][ldy]
+  T* tiles = reinterpret_cast<T*>(smraw);       // [2 buffers][re, im][NB][ldy]
   const int TS = 2 * NB * ldy;
   T* tbs = tiles + 2 * TS;                      // [2][NB][NB] complex: lambda2 T_{q' q} inside the block, q' < q
   T* tns = tbs + 4 * NB * NB;                   // [2][NB][NB] complex: lambda2 T_{q j} towards the block after
@@ -361,14 +354,13 @@ __global__ __launch_bounds__(SWT * SL, SL == 1 ? MINB : 1) void k_schur_sweep(
   // (q R + i) 64 + l (conflict-free), read back by the next step's near coupling
   Cx<T>* wsol = reinterpret_cast<Cx<T>*>(tns + 4 * NB * NB);
 
-  const int t = t0 + (int)blockIdx.x * SL + half;   // slice = (right-hand side, frequency)
-  const int n = t % F;
-  T* slice = spec + (int64_t)t * sy * 2 * sx;
+  const int n = blockIdx.x, b = blockIdx.y;
+  T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
   const T* tre = tup;
   const T* tim = tup + (int64_t)sx * sx;
   const double2 l2 = lam[F + n];
   const T l2r = (T)l2.x, l2i = (T)l2.y;
-  const int wave = tx >> 6;
+  const int wave = threadIdx.x >> 6;
   const int nblk = (sx + NB - 1) / NB;
 
   // lambda2 T[k0a + qa][k0b + qb] for qa, qb < NB (zero outside the valid
@@ -388,8 +380,8 @@ __global__ __launch_bounds__(SWT * SL, SL == 1 ? MINB : 1) void k_schur_sweep(
 
   {  // prologue: the last block (the only one that may be partial)
     const int k0 = (nblk - 1) * NB, nk = sx - k0;
-    tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, tx, SWT);
-    stage_coef(tbs, k0, k0, nk, true, tx, SWT);
+    tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
+    stage_coef(tbs, k0, k0, nk, true, (int)threadIdx.x, SWT);
   }
   __syncthreads();
 
@@ -397,7 +389,7 @@ __global__ __launch_bounds__(SWT * SL, SL == 1 ? MINB : 1) void k_schur_sweep(
     // Thread indices re-derived each step from an opaque copy: otherwise the
     // compiler hoists every per-thread address of the tile copies out of the
     // loop and keeps them all live, which spills the solve's registers.
-    int tid = tx;
+    int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int cur = st & 1, nxt = cur ^ 1;
@@ -590,7 +582,7 @@ __global__ __launch_bounds__(SWT * SL, SL == 1 ? MINB : 1) void k_schur_sweep(
   {  // the first block, solved in the last step
     const int nkp = min(NB, sx);
     T* pre = tiles + ((nblk - 1) & 1) * TS;
-    tile_store_by(slice, pre, pre + NB * ldy, 0, nkp, NB, sx, sy, ldy, R, tx, SWT);
+    tile_store_by(slice, pre, pre + NB * ldy, 0, nkp, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
   }
 }
 
@@ -870,8 +862,6 @@ void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
                                          op.lo, op.di, op.up, g.F, g.sx, g.sy, sh.ldy);
 }
 
-constexpr size_t kCuLds = 160 * 1024;   // LDS bytes per CU (gfx950)
-
 // Pipelined kernel: LDS bytes of two tiles and two coupling blocks.
 template <typename T, int NB>
 size_t piped_lds(const SweepShape& sh) {
@@ -880,35 +870,19 @@ size_t piped_lds(const SweepShape& sh) {
 }
 
 template <typename T, int R, int P, int NB, int RB, int W0B>
-void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int t0, int count,
-                  bool dual) {
+void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, 16>(pl);
-  const size_t lds = (piped_lds<T, NB>(sh) + 15) & ~(size_t)15;
+  const size_t lds = piped_lds<T, NB>(sh);
   // two workgroups per CU where the registers allow (lines of up to 256 rows):
   // an odd number of slices, or more slices than CUs, then leaves no CU idle
   // while a last slice runs alone
   constexpr int MINB = (R == 4) ? 2 : 1;
-  if (!dual) {
-    auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B, 1>
-                      : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B, 1>;
-    hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    kfn<<<dim3((unsigned)count), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo,
-                                                 op.up, g.F, g.sx, g.sy, sh.ldy, t0, (int)lds);
-    return;
-  }
-  if constexpr (MINB == 2) {
-    // two slices per workgroup, and more LDS requested than the two use, so
-    // that no other workgroup of the sweep or of the x-transform can share
-    // the CU: the pairs run on CUs of their own, beside the single slices
-    const size_t req = std::max(2 * lds, (size_t)kCuLds - lds + 1024);
-    auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B, 2>
-                      : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B, 2>;
-    hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)req);
-    kfn<<<dim3((unsigned)(count / 2)), 2 * SWT, req, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu,
-                                                          op.lo, op.up, g.F, g.sx, g.sy, sh.ldy, t0,
-                                                          (int)lds);
-  }
+  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B>
+                    : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B>;
+  hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
+                                       g.F, g.sx, g.sy, sh.ldy);
 }
 
 // (NB, BK) of the wide kernel per precision and row count.
@@ -927,7 +901,7 @@ template <> struct PipedCfg<double> { static constexpr int NB4 = 0, NB8 = 0; };
 // MFMA rate) is the long pole, and there all four waves run it.
 
 template <typename T>
-void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int t0, int count, bool dual) {
+void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   using C = SweepCfg<T>;
   using PC = PipedCfg<T>;
   SweepShape sh = sweep_shape<T, C::NB, C::BK>(pl);
@@ -937,7 +911,7 @@ void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int t0, i
     // <= 256: 1 + 3 x 5, <= 512: 2 + 3 x 10
 #define PD_PIPED(RR, PP, BB, W0, NBV)                                                     \
   if (sh.R == RR && sh.P == PP) {                                                         \
-    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s, t0, count, dual);               \
+    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s);                                \
     return;                                                                               \
   }
     PD_PIPED(4, 1, 2, 0, PC::NB4) PD_PIPED(4, 2, 2, 0, PC::NB4) PD_PIPED(4, 4, 2, 0, PC::NB4)
@@ -947,10 +921,8 @@ void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int t0, i
 #undef PD_PIPED
     return;
   }
-  // float64: the one-phase kernel (block in LDS, coupling on all four waves),
-  // always over every slice (schur_sweep_pairs never splits it)
+  // float64: the one-phase kernel (block in LDS, coupling on all four waves)
   if constexpr (PC::NB8 == 0) {
-    (void)t0; (void)count; (void)dual;
 #define PD_SWEEP(RR, PP, BB)                                                              \
   if (sh.R == RR && sh.P == PP && sh.RB == BB) {                                          \
     launch_one<T, RR, PP, C::NB, C::BK, BB>(pl, op, spec, s);                             \
@@ -984,21 +956,9 @@ void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {
     k_line_lu<float><<<grid, NT, 0, s>>>((float*)op.lu, pl.d_lam, op.tk, op.lo, op.di, op.up, g.F, g.sx, g.sy);
 }
 
-int schur_sweep_pairs(const Plan& pl) {
-  if (pl.prec == Prec::F64) return 0;
-  const SweepShape a = sweep_shape<float, 16, 32>(pl);
-  if (a.R != 4) return 0;   // one workgroup per CU: no pairs to set apart
-  const int W = pl.g.F * pl.g.B, cu = pl.num_cu;
-  const int extra = W - cu;
-  return (extra >= 1 && extra <= cu / 8) ? extra : 0;
-}
-
-void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s, int t0, int count,
-                 bool dual) {
-  if (count < 0) count = pl.g.F * pl.g.B - t0;
-  if (count <= 0) return;
-  if (pl.prec == Prec::F64) launch<double>(pl, op, (double*)spec, s, t0, count, dual);
-  else launch<float>(pl, op, (float*)spec, s, t0, count, dual);
+void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
+  if (pl.prec == Prec::F64) launch<double>(pl, op, (double*)spec, s);
+  else launch<float>(pl, op, (float*)spec, s);
 }
 
 }  // namespace pd

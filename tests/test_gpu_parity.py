@@ -85,37 +85,6 @@ def test_schur_sweep_shapes(nx, ny, prec):
     assert err < PREC_TOL[prec]
 
 
-# More slices than CUs by a few (nt = 512: 257 frequencies; nt = 256 with two
-# right-hand sides: 258 slices): the last slices run as pairs on a second
-# stream beside the others, each side followed by its own inverse x-transform.
-@pytest.mark.parametrize("nt,batch", [(512, 1), (256, 2)])
-def test_schur_sweep_pairs(nt, batch):
-    announce(f"sweep pairs nt={nt} batch={batch}")
-    cfg = dict(dim=2, nx=16, ny=12, nt=nt, scheme="tr", T=1.0, nu=0.05, ax=1.0, ay=0.5, alpha=1e-3)
-    torch, pd, prob = make(cfg, "fp32", batch=batch)
-    rng = np.random.default_rng(17)
-    r = rng.standard_normal((batch, prob.nt, prob.nspace))
-    z = pd.apply_precond(to_gpu(torch, r, pd.shape))
-    torch.cuda.synchronize()
-    zh = z.cpu().numpy().reshape(batch, prob.nt, -1)
-    for i in range(batch):
-        err = rel_err(zh[i], o_prec.three_steps(prob, r[i]))
-        print(f"  rhs {i} rel err {err:.3e}")
-        assert err < PREC_TOL["fp32"]
-    # and inside a solve, with the stage timing of both streams
-    pd.set_timing(True)
-    b = to_gpu(torch, r, pd.shape)
-    u, res = pd.solve(b, rtol=1e-10, max_iter=30)
-    st = pd.stage_times(reset=True)
-    pd.set_timing(False)
-    assert res.converged
-    assert st["line_pairs"][1] >= 1 and st["line_solve"][1] == st["line_pairs"][1]
-    ub = u.cpu().numpy().reshape(batch, prob.nt, -1)
-    for i in range(batch):
-        true_res = np.linalg.norm(r[i] - ops.apply_A(prob, ub[i])) / np.linalg.norm(r[i])
-        assert true_res <= 1.01e-10
-
-
 # Line-solver shapes (sine basis): lines of 256 .. 512 rows take 8 rows per
 # lane (32 or 64 lanes per line), a ragged length pads the last lane, and an
 # x-size that is not a multiple of 4 takes the element-wise tile copies.
