@@ -98,22 +98,24 @@ def run_precision(cfg, prec, args, torch):
     from paper_2005_09158_amd import ParaDiag
     # the FGMRES workspace holds restart+1 float64 and restart preconditioned
     # vectors: a shorter restart where the requested one does not fit in HBM
+    # (with the right-hand side, the solution and the source term beside it)
     restart, pd = args.restart, None
     while pd is None:
         try:
             pd = ParaDiag(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, scheme=cfg.scheme, T=cfg.T,
                           nu=cfg.nu, ax=cfg.ax, ay=cfg.ay, alpha=cfg.alpha, batch=cfg.batch,
                           prec=prec, restart=restart)
+            U0, u1, f = make_inputs(cfg, torch, pd)
+            b = pd.build_rhs(U0, u1, f)
+            del f
+            u = torch.empty_like(b)
         except torch.OutOfMemoryError:
+            pd = U0 = u1 = f = b = None
             torch.cuda.empty_cache()
             if restart <= 2:
                 raise
             restart -= 1
-            print(f"[bench] {prec}: workspace does not fit, restart {restart}", file=sys.stderr, flush=True)
-    U0, u1, f = make_inputs(cfg, torch, pd)
-    b = pd.build_rhs(U0, u1, f)
-    del f
-    u = torch.empty_like(b)
+            print(f"[bench] {prec}: does not fit in HBM, restart {restart}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         pd.solve(b, u, rtol=cfg.rtol, max_iter=200, restart=restart)
     # one solve with every stage timed, outside the timed region: the per-stage
