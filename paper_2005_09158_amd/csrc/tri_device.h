@@ -80,24 +80,34 @@ __device__ void tri_wave(Cx<T> (&d)[R], Cx<T> a, Cx<T> b, Cx<T> c, int N, int p)
   Cx<T> aA = aa[R - 1], gA = cc[R - 1], dA = d[R - 1];
   Cx<T> aBn = shdn(aB, 1, P), gBn = shdn(gB, 1, P), dBn = shdn(dB, 1, P);
   if (p == P - 1) { aBn = cz<T>(); gBn = cz<T>(); dBn = cz<T>(); }
-  // eliminate the first-row unknowns: tridiagonal system in x_e across lanes
+  // eliminate the first-row unknowns: tridiagonal system in x_e across lanes,
+  // each equation scaled to a unit diagonal, so that cyclic reduction moves
+  // three coefficients per neighbour and takes one reciprocal per level
   Cx<T> A = (p == 0) ? cz<T>() : neg(mul(aA, aB));
   Cx<T> Bc = sub(sub(c1<T>(), mul(aA, gB)), mul(gA, aBn));
   Cx<T> Cc = neg(mul(gA, gBn));
   Cx<T> D = sub(sub(dA, mul(aA, dB)), mul(gA, dBn));
+  {
+    const Cx<T> ib = rcp(Bc);
+    A = mul(A, ib);
+    Cc = mul(Cc, ib);
+    D = mul(D, ib);
+  }
 #pragma unroll
   for (int s = 1; s < P; s <<= 1) {
-    Cx<T> Am = shup(A, s, P), Bm = shup(Bc, s, P), Cm = shup(Cc, s, P), Dm = shup(D, s, P);
-    Cx<T> Ap = shdn(A, s, P), Bp = shdn(Bc, s, P), Cp = shdn(Cc, s, P), Dp = shdn(D, s, P);
-    if (p < s) { Am = cz<T>(); Bm = c1<T>(); Cm = cz<T>(); Dm = cz<T>(); }
-    if (p + s >= P) { Ap = cz<T>(); Bp = c1<T>(); Cp = cz<T>(); Dp = cz<T>(); }
-    Cx<T> k1 = mul(A, rcp(Bm)), k2 = mul(Cc, rcp(Bp));
-    A = neg(mul(k1, Am));
-    Cc = neg(mul(k2, Cp));
-    Bc = sub(sub(Bc, mul(k1, Cm)), mul(k2, Ap));
-    D = sub(sub(D, mul(k1, Dm)), mul(k2, Dp));
+    Cx<T> Am = shup(A, s, P), Cm = shup(Cc, s, P), Dm = shup(D, s, P);
+    Cx<T> Ap = shdn(A, s, P), Cp = shdn(Cc, s, P), Dp = shdn(D, s, P);
+    if (p < s) { Am = cz<T>(); Cm = cz<T>(); Dm = cz<T>(); }       // x = 0 outside the line
+    if (p + s >= P) { Ap = cz<T>(); Cp = cz<T>(); Dp = cz<T>(); }
+    // row - A row_{p-s} - C row_{p+s}, then rescaled to a unit diagonal
+    const Cx<T> ib = rcp(sub(sub(c1<T>(), mul(A, Cm)), mul(Cc, Ap)));
+    const Cx<T> nA = neg(mul(A, Am)), nC = neg(mul(Cc, Cp));
+    const Cx<T> nD = sub(sub(D, mul(A, Dm)), mul(Cc, Dp));
+    A = mul(nA, ib);
+    Cc = mul(nC, ib);
+    D = mul(nD, ib);
   }
-  Cx<T> xe = mul(D, rcp(Bc));
+  Cx<T> xe = D;
   Cx<T> xem = shup(xe, 1, P);
   if (p == 0) xem = cz<T>();
   Cx<T> xs = sub(sub(dB, mul(aB, xem)), mul(gB, xe));
