@@ -133,30 +133,36 @@ __device__ __forceinline__ void coupling_direct(const T* slice, const T* tre, co
   }
 }
 
-// Fragments of one 16-mode step of the coupling product: T rows of this
-// lane's output column and RB rows of solved lines (real, imaginary parts).
-template <typename T, int RB> struct CouplingFrag {
-  typename V4<T>::t tr, ti, ar[RB], ai[RB];
+// Fragments of one 16-mode step of the coupling product: the T rows of this
+// lane's output column for each of NTB blocks of output modes, and RB rows of
+// solved lines (real, imaginary parts).
+template <typename T, int RB, int NTB> struct CouplingFrag {
+  typename V4<T>::t tr[NTB], ti[NTB], ar[RB], ai[RB];
 };
 
-template <typename T, int RB, bool VEC>
-__device__ __forceinline__ void load_frag(CouplingFrag<T, RB>& f, const T* slice, const T* trow,
-                                          const T* irow, int sx, int sy, int j, bool qok, int r0) {
+// Loads modes j .. j+3 (those below je) of the fragment.
+template <typename T, int RB, int NTB, bool VEC>
+__device__ __forceinline__ void load_frag(CouplingFrag<T, RB, NTB>& f, const T* slice,
+                                          const T* const (&trow)[NTB], const T* const (&irow)[NTB],
+                                          const bool (&tok)[NTB], int sx, int sy, int j, int je, int r0) {
   using Q4 = typename V4<T>::t;
-  const bool jok = j < sx;
-  f.tr = Q4{};
-  f.ti = Q4{};
-  if (qok && jok) {
-    f.tr = load4(trow, j, sx, VEC);
-    f.ti = load4(irow, j, sx, VEC);
+  const bool jok = j < je;
+#pragma unroll
+  for (int tb = 0; tb < NTB; ++tb) {
+    f.tr[tb] = Q4{};
+    f.ti[tb] = Q4{};
+    if (tok[tb] && jok) {
+      f.tr[tb] = load4(trow[tb], j, je, VEC);
+      f.ti[tb] = load4(irow[tb], j, je, VEC);
+    }
   }
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
     const int r = r0 + 16 * i;
     if (jok && r < sy) {
       const T* row = slice + (int64_t)r * 2 * sx;
-      f.ar[i] = load4(row, j, sx, VEC);
-      f.ai[i] = load4(row + sx, j, sx, VEC);
+      f.ar[i] = load4(row, j, je, VEC);
+      f.ai[i] = load4(row + sx, j, je, VEC);
     } else {
       f.ar[i] = Q4{};
       f.ai[i] = Q4{};
@@ -164,55 +170,72 @@ __device__ __forceinline__ void load_frag(CouplingFrag<T, RB>& f, const T* slice
   }
 }
 
-template <typename T, int NB, int RB>
-__device__ __forceinline__ void mma_frag(const CouplingFrag<T, RB>& f, int part,
-                                         typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+template <typename T, int NB, int RB, int NTB>
+__device__ __forceinline__ void mma_frag(const CouplingFrag<T, RB, NTB>& f, int part,
+                                         typename SweepMfma<T>::acc_t (&acc)[NTB][RB][2 * NB / 16]) {
   using MF = SweepMfma<T>;
   constexpr int NCB = 2 * NB / 16;
-  const T trv[4] = {f.tr.x, f.tr.y, f.tr.z, f.tr.w}, tiv[4] = {f.ti.x, f.ti.y, f.ti.z, f.ti.w};
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const T b_re_r = trv[st], b_re_i = -tiv[st], b_im_r = tiv[st], b_im_i = trv[st];
+    T b_re_r[NTB], b_re_i[NTB], b_im_r[NTB], b_im_i[NTB];
+#pragma unroll
+    for (int tb = 0; tb < NTB; ++tb) {
+      const T tr = (st == 0) ? f.tr[tb].x : (st == 1) ? f.tr[tb].y : (st == 2) ? f.tr[tb].z : f.tr[tb].w;
+      const T ti = (st == 0) ? f.ti[tb].x : (st == 1) ? f.ti[tb].y : (st == 2) ? f.ti[tb].z : f.ti[tb].w;
+      b_re_r[tb] = tr; b_re_i[tb] = -ti; b_im_r[tb] = ti; b_im_i[tb] = tr;
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       const T av_r = (st == 0) ? f.ar[i].x : (st == 1) ? f.ar[i].y : (st == 2) ? f.ar[i].z : f.ar[i].w;
       const T av_i = (st == 0) ? f.ai[i].x : (st == 1) ? f.ai[i].y : (st == 2) ? f.ai[i].z : f.ai[i].w;
-      if constexpr (NCB == 2) {
-        acc[i][0] = MF::run(av_r, b_re_r, acc[i][0]);
-        acc[i][0] = MF::run(av_i, b_re_i, acc[i][0]);
-        acc[i][1] = MF::run(av_r, b_im_r, acc[i][1]);
-        acc[i][1] = MF::run(av_i, b_im_i, acc[i][1]);
-      } else {
-        acc[i][0] = MF::run(av_r, part ? b_im_r : b_re_r, acc[i][0]);
-        acc[i][0] = MF::run(av_i, part ? b_im_i : b_re_i, acc[i][0]);
+#pragma unroll
+      for (int tb = 0; tb < NTB; ++tb) {
+        if constexpr (NCB == 2) {
+          acc[tb][i][0] = MF::run(av_r, b_re_r[tb], acc[tb][i][0]);
+          acc[tb][i][0] = MF::run(av_i, b_re_i[tb], acc[tb][i][0]);
+          acc[tb][i][1] = MF::run(av_r, b_im_r[tb], acc[tb][i][1]);
+          acc[tb][i][1] = MF::run(av_i, b_im_i[tb], acc[tb][i][1]);
+        } else {
+          acc[tb][i][0] = MF::run(av_r, part ? b_im_r[tb] : b_re_r[tb], acc[tb][i][0]);
+          acc[tb][i][0] = MF::run(av_i, part ? b_im_i[tb] : b_re_i[tb], acc[tb][i][0]);
+        }
       }
     }
   }
 }
 
-// Coupling to the solved modes j >= kend with W read from global memory, the
-// fragments of the next 16 modes loaded while the current ones multiply.
-template <typename T, int NB, int RB, bool VEC>
+// Coupling of NTB blocks of output modes (block tb: rows k0t[tb] .. of T,
+// skipped where tok[tb] is false) to the solved modes jb <= j < je, with W
+// read from global memory and the fragments of the next 16 modes loaded while
+// the current ones multiply.  With NTB = 2 every W fragment feeds both blocks.
+template <typename T, int NB, int RB, int NTB, bool VEC>
 __device__ __forceinline__ void coupling_far(const T* slice, const T* tre, const T* tim, int sx, int sy,
-                                             int k0n, int kend, int y0, int lr, int lk,
-                                             typename SweepMfma<T>::acc_t (&acc)[RB][2 * NB / 16]) {
+                                             const int (&k0t)[NTB], const bool (&tok)[NTB], int jb,
+                                             int je, int y0, int lr, int lk,
+                                             typename SweepMfma<T>::acc_t (&acc)[NTB][RB][2 * NB / 16]) {
   constexpr int NCB = 2 * NB / 16;
   const int q = (NCB == 2) ? lr : (lr & 7);
   const int part = (NCB == 2) ? 0 : (lr >> 3);
-  const T* trow = tre + (int64_t)(k0n + q) * sx;
-  const T* irow = tim + (int64_t)(k0n + q) * sx;
+  const T* trow[NTB];
+  const T* irow[NTB];
+#pragma unroll
+  for (int tb = 0; tb < NTB; ++tb) {
+    const int64_t off = tok[tb] ? (int64_t)(k0t[tb] + q) * sx : 0;
+    trow[tb] = tre + off;
+    irow[tb] = tim + off;
+  }
   const int r0 = y0 + lr;
-  if (kend >= sx) return;
-  CouplingFrag<T, RB> fa, fb;
-  load_frag<T, RB, VEC>(fa, slice, trow, irow, sx, sy, kend + 4 * lk, true, r0);
+  if (jb >= je) return;
+  CouplingFrag<T, RB, NTB> fa, fb;
+  load_frag<T, RB, NTB, VEC>(fa, slice, trow, irow, tok, sx, sy, jb + 4 * lk, je, r0);
 #pragma unroll 1
-  for (int j0 = kend; j0 < sx; j0 += 32) {
-    const bool more = j0 + 16 < sx;
-    if (more) load_frag<T, RB, VEC>(fb, slice, trow, irow, sx, sy, j0 + 16 + 4 * lk, true, r0);
-    mma_frag<T, NB, RB>(fa, part, acc);
+  for (int j0 = jb; j0 < je; j0 += 32) {
+    const bool more = j0 + 16 < je;
+    if (more) load_frag<T, RB, NTB, VEC>(fb, slice, trow, irow, tok, sx, sy, j0 + 16 + 4 * lk, je, r0);
+    mma_frag<T, NB, RB, NTB>(fa, part, acc);
     if (!more) break;
-    if (j0 + 32 < sx) load_frag<T, RB, VEC>(fa, slice, trow, irow, sx, sy, j0 + 32 + 4 * lk, true, r0);
-    mma_frag<T, NB, RB>(fb, part, acc);
+    if (j0 + 32 < je) load_frag<T, RB, NTB, VEC>(fa, slice, trow, irow, tok, sx, sy, j0 + 32 + 4 * lk, je, r0);
+    mma_frag<T, NB, RB, NTB>(fb, part, acc);
   }
 }
 
@@ -331,7 +354,10 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
 //   * meanwhile waves 1..NCW stage block b-1's tile and subtract lambda2 times
 //     its coupling to all modes beyond block b (MFMA products on fragments
 //     read from global memory, one 16-mode step prefetched), and stage the
-//     coefficients block b-1 needs: lambda2 T inside it and towards block b;
+//     coefficients block b-1 needs: lambda2 T inside it and towards block b.
+//     Every other step the pass over the modes beyond block b also produces
+//     block b-2's coupling to them, which the next step completes with block
+//     b's modes alone: the solved lines are streamed once per two blocks;
 //   * barrier.
 // Tiles and coefficient blocks are double-buffered in LDS.  One wave per SIMD
 // per workgroup; with NB = 8 two workgroups share a CU.
@@ -362,6 +388,22 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
   const T l2r = (T)l2.x, l2i = (T)l2.y;
   const int wave = threadIdx.x >> 6;
   const int nblk = (sx + NB - 1) / NB;
+  // Far couplings come in pairs of blocks: in a step with far set, the rows a
+  // wave prepares get their coupling to every mode beyond block kb for blocks
+  // kb-1 and kb-2 in one pass over those modes (each W fragment read once,
+  // multiplied twice); block kb-2's part waits in carry until the next step,
+  // which adds only its coupling to block kb.  Neighbouring slices take
+  // opposite parities, so half the workgroups stream the solved lines at any
+  // time.
+  constexpr int RBC = RB > W0B ? RB : W0B;
+  typename MF::acc_t carry[RBC][NCB];
+#pragma unroll
+  for (int i = 0; i < RBC; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) carry[i][j][v] = 0;
+  const int phase = (int)(blockIdx.x & 1);
 
   // lambda2 T[k0a + qa][k0b + qb] for qa, qb < NB (zero outside the valid
   // range: qb >= nkb, or qa >= qb when the two blocks coincide)
@@ -405,6 +447,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
     __syncthreads();   // block kb+1 in global memory; its LDS buffer is free
     const int k0n = k0 - NB;   // next block (always full) when kb > 0
+    const bool far = ((st + phase) & 1) == 0;
     // Rows [y0, y1) of block kb-1: staged into the LDS buffer, coupled to every
     // mode beyond block kb (read from global memory), and lambda2 times the
     // coupling subtracted.  One wave; it touches only its own rows.
@@ -412,13 +455,41 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       constexpr int RBX = decltype(rbx)::value;
       tile_rows_load<T, NB, RBX * 16, VEC>(slice, nre, nim, k0n, sx, y0, y1, ldy, R, lane);
       typename MF::acc_t acc[RBX][NCB];
+      if (far) {   // blocks kb-1 and kb-2 against every mode beyond block kb
+        typename MF::acc_t a2[2][RBX][NCB];
 #pragma unroll
-      for (int i = 0; i < RBX; ++i)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < NCB; ++j)
+          for (int i = 0; i < RBX; ++i)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
-      coupling_far<T, NB, RBX, VEC>(slice, tre, tim, sx, sy, k0n, kend, y0, lr, lk, acc);
+            for (int j = 0; j < NCB; ++j)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) a2[h][i][j][v] = 0;
+        const int k0t[2] = {k0n, k0n - NB};
+        const bool tok[2] = {true, k0n >= NB};
+        coupling_far<T, NB, RBX, 2, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, sx, y0, lr, lk, a2);
+#pragma unroll
+        for (int i = 0; i < RBX; ++i)
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) {
+            acc[i][j] = a2[0][i][j];
+            carry[i][j] = a2[1][i][j];
+          }
+      } else {     // block kb-1: the carried part plus its coupling to block kb+1
+        typename MF::acc_t a1[1][RBX][NCB];
+#pragma unroll
+        for (int i = 0; i < RBX; ++i)
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) a1[0][i][j] = carry[i][j];
+        const int k0t[1] = {k0n};
+        const bool tok[1] = {true};
+        coupling_far<T, NB, RBX, 1, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, min(kend + NB, sx), y0,
+                                         lr, lk, a1);
+#pragma unroll
+        for (int i = 0; i < RBX; ++i)
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) acc[i][j] = a1[0][i][j];
+      }
       // tile -= lambda2 C: all LDS reads first, then all writes (one
       // read-modify-write at a time would expose the LDS latency per value)
       const bool col_ok = NCB == 2 || lr < 8;
