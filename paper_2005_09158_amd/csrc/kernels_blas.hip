@@ -446,6 +446,49 @@ __global__ __launch_bounds__(NT) void k_xupd(const Tz* __restrict__ Z, int64_t z
   }
 }
 
+// The same update, four consecutive elements per thread with every Z load of
+// an iteration issued before the first use (NZ known at compile time; N1 a
+// multiple of 4 and Z rows 16-byte aligned).
+template <typename Tz> struct Quad;
+template <> struct Quad<float> {
+  static __device__ __forceinline__ void load(const float* p, double (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+};
+template <> struct Quad<double> {
+  static __device__ __forceinline__ void load(const double* p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0], c = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = c.x; v[3] = c.y;
+  }
+};
+
+template <typename Tz, int NZ>
+__global__ __launch_bounds__(NT) void k_xupd4(const Tz* __restrict__ Z, int64_t zstride,
+                                              const double* __restrict__ yc, int ldy,
+                                              double* __restrict__ x, int64_t N1, int overwrite) {
+  const int b = blockIdx.y;
+  double cf[NZ];
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) cf[i] = yc[b * ldy + i];
+  const int64_t n4 = N1 / 4;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n4; e += (int64_t)gridDim.x * NT) {
+    const int64_t off = (int64_t)b * N1 + 4 * e;
+    double z[NZ][4];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) Quad<Tz>::load(Z + i * zstride + off, z[i]);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!overwrite) Quad<double>::load(x + off, v);
+#pragma unroll
+    for (int i = 0; i < NZ; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = fma(cf[i], z[i][c], v[c]);
+    double2* xo = reinterpret_cast<double2*>(x + off);
+    xo[0] = double2{v[0], v[1]};
+    xo[1] = double2{v[2], v[3]};
+  }
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) b[e] = a[e];
 }
@@ -570,6 +613,19 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
               const double* y, double* x, bool overwrite, hipStream_t s) {
+  if (pl.g.N1 % 4 == 0 && zstride % 4 == 0 && nz >= 1 && nz <= 8 && (uintptr_t)x % 16 == 0 &&
+      (uintptr_t)Z % 16 == 0) {
+    dim3 grid(grid_for(pl.g.N1 / 4), pl.g.B);
+#define PD_XUPD(K)                                                                                  \
+  case K:                                                                                           \
+    if (z_is_f32)                                                                                   \
+      k_xupd4<float, K><<<grid, NT, 0, s>>>((const float*)Z, zstride, y, MAXV, x, pl.g.N1, overwrite); \
+    else                                                                                            \
+      k_xupd4<double, K><<<grid, NT, 0, s>>>((const double*)Z, zstride, y, MAXV, x, pl.g.N1, overwrite); \
+    return;
+    switch (nz) { PD_XUPD(1) PD_XUPD(2) PD_XUPD(3) PD_XUPD(4) PD_XUPD(5) PD_XUPD(6) PD_XUPD(7) PD_XUPD(8) }
+#undef PD_XUPD
+  }
   dim3 grid(grid_for(pl.g.N1), pl.g.B);
   if (z_is_f32)
     k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
