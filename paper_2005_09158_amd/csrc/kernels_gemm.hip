@@ -204,11 +204,16 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
                                                   const unsigned short* __restrict__ Bt,
                                                   float* __restrict__ C, int64_t M, int N, int K,
                                                   int ntn, int64_t nblocks) {
-  constexpr int BM = 128, BN = 128, BK = 32, LD = BK + 8;   // LDS row: 80 bytes
+  constexpr int BM = 128, BN = 128, BK = 32;
+  // LDS rows of BK bf16 (64 bytes, four 16-byte chunks); chunk c of row r is
+  // stored at position c ^ ((r >> 1) & 3), so that the eight rows one
+  // fragment read touches per LDS cycle (and the rows of a staging write)
+  // fall on distinct banks
+  auto off = [](int r, int ch) { return r * BK + 8 * (ch ^ ((r >> 1) & 3)); };
   // operand terms: 1 (plain bf16), 2 (hi + lo), 3 (hi + mid + lo)
   constexpr int NA = (SPLIT == 6) ? 3 : (SPLIT == 3) ? 2 : 1;
-  __shared__ __align__(16) unsigned short As[NA][BM * LD];
-  __shared__ __align__(16) unsigned short Bs[NA][BN * LD];
+  __shared__ __align__(16) unsigned short As[NA][BM * BK];
+  __shared__ __align__(16) unsigned short Bs[NA][BN * BK];
 
   int64_t bid = blockIdx.x;
   if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);   // XCD-aware order
@@ -259,13 +264,13 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
         }
       }
 #pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<us4*>(&As[a][r * LD + c]) = part[a];
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<us4*>(&As[a][off(r, c >> 3) + (c & 7)]) = part[a];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a][r * LD + c]) = rb[a][i];
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a][off(r, c >> 3)]) = rb[a][i];
     }
   };
 
@@ -286,10 +291,10 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
     for (int x = 0; x < NA; ++x) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        a[x][i] = *reinterpret_cast<const bf8*>(&As[x][(wm0 + 16 * i + lr) * LD + 8 * lk]);
+        a[x][i] = *reinterpret_cast<const bf8*>(&As[x][off(wm0 + 16 * i + lr, lk)]);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x][(wn0 + 16 * j + lr) * LD + 8 * lk]);
+        b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x][off(wn0 + 16 * j + lr, lk)]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
