@@ -318,12 +318,14 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   { Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, fft_flops(pl)); fft_time_inverse(pl, pl.spec_a, out, out_f32, accumulate, variant, s); }
 }
 
+// y = b - A u (A u without b); with `sq`, also the partial sums of y . y, one
+// per matvec workgroup (reduced with matvec_chunks)
 static void apply_A(Plan& pl, int variant, const void* u, bool u_f32, const double* b, double* y,
-                    hipStream_t s) {
+                    hipStream_t s, double* sq = nullptr) {
   const double n = (double)pl.g.NA;
   Timed t(pl, PD_STAGE_MATVEC, s, n * ((u_f32 ? 4.0 : 8.0) + 8.0 + (b ? 8.0 : 0.0)),
-          n * (pl.L == 3 ? 22.0 : 18.0));
-  matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s);
+          n * ((pl.L == 3 ? 22.0 : 18.0) + (sq ? 2.0 : 0.0)));
+  matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s, nullptr, 0, sq ? 1 : 0, sq);
 }
 
 namespace {
@@ -349,10 +351,6 @@ Small carve_small(Plan& pl, char*& p) {
   return sm;
 }
 
-// Reduction kernels take sigma per slot; slots >= nscale use 1.  We keep a
-// device vector of ones at the tail of sigma for that purpose by launching the
-// reduction with sigma == nullptr for unscaled sums.
-void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s);
 }  // namespace
 static void timed_dot(Plan& pl, const double* V, int64_t vs, int nv, const double* w, double* part,
                       hipStream_t s) {
@@ -367,9 +365,9 @@ static void timed_update(Plan& pl, const double* V, int64_t vs, int nv, const do
   update_dot(pl, V, vs, nv, coef, w, part, dots, s);
 }
 static void timed_reduce(Plan& pl, const double* part, int nv, const double* sigma, int nscaled,
-                         double* h, double* coef, hipStream_t s) {
+                         double* h, double* coef, hipStream_t s, int chunks = 0) {
   Timed t(pl, PD_STAGE_OTHER, s);
-  reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s);
+  reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks);
 }
 namespace {
 // Pinned host staging of the solvers' small transfers: [norms | h1 h2 | sigma | y],
@@ -391,8 +389,9 @@ double* pinned(Plan& pl) {
   return pl.pin;
 }
 
-void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s) {
-  timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s);
+// chunks: partial sums per right-hand side in sm.partial (<= 0: dot_chunks)
+void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s, int chunks = 0) {
+  timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s, chunks);
   double* tmp = pl.pin;   // norms region
   hipMemcpyAsync(tmp, sm.nrm, sizeof(double) * pl.g.B * MAXV, hipMemcpyDeviceToHost, s);
   hipStreamSynchronize(s);
@@ -401,10 +400,6 @@ void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s) {
   for (int b = 0; b < pl.g.B; ++b) out[b] = std::sqrt(std::fabs(tmp[(size_t)b * MAXV]));
 }
 
-void norms(Plan& pl, const double* v, Small& sm, std::vector<double>& out, hipStream_t s) {
-  timed_dot(pl, v, 0, 1, v, sm.partial, s);
-  norms_from(pl, sm, out, s);
-}
 
 }  // namespace
 
@@ -490,8 +485,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     // residual of the result with respect to A (reported, not iterated)
     std::vector<double> nr;
     double* rv = (double*)p;
-    apply_A(pl, variant, u, false, b, rv, s);
-    norms(pl, rv, sm, nr, s);
+    apply_A(pl, variant, u, false, b, rv, s, sm.partial);
+    norms_from(pl, sm, nr, s, matvec_chunks(pl));
     rel(nr);
     push_hist(*std::max_element(res.begin(), res.end()));
     return finish(true);
@@ -502,8 +497,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     if (!o->use_x0) fill_zero(u, g.NA, s);
     std::vector<double> nr;
     while (true) {
-      apply_A(pl, variant, u, false, b, r, s);
-      norms(pl, r, sm, nr, s);
+      apply_A(pl, variant, u, false, b, r, s, sm.partial);
+      norms_from(pl, sm, nr, s, matvec_chunks(pl));
       bool all = rel(nr);
       for (int i = 0; i < B; ++i)
         if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
@@ -543,8 +538,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       nr = bn;
     } else {
       if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
-      apply_A(pl, variant, u, false, b, Vj(0), s);
-      norms(pl, Vj(0), sm, nr, s);
+      apply_A(pl, variant, u, false, b, Vj(0), s, sm.partial);
+      norms_from(pl, sm, nr, s, matvec_chunks(pl));
     }
     first = false;
     bool all = rel(nr);

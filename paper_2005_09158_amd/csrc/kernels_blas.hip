@@ -164,6 +164,24 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
 #pragma unroll
     for (int v = 0; v < V; ++v) { u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = uu[v]; k1[v] = kk[v]; }
   }
+  // dots of the values r just written (at element offset off) with V_q; with
+  // NV == 1 and no V, the squared norm of the output itself
+  auto dots_of = [&](const double (&r)[V], int64_t off) {
+    if (NV == 1 && Vk == nullptr) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[0] += r[v] * r[v];
+      return;
+    }
+    const double* Vb = Vk + boff;
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (NV > 0 || q < nv) {
+        double vq[V];
+        ldv<double, V>(Vb + q * vstride + off, vq);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[q] += vq[v] * r[v];
+      }
+  };
   // two time steps per iteration, all of both steps' loads issued first (the
   // second step of an odd tail re-reads the first and is not stored)
   const int cnt = nend - nbeg;
@@ -181,30 +199,10 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
     }
     double rA[V], rB[V];
     march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA, rA);
-    if constexpr (NV != 0) {
-      const double* Vb = Vk + boff;
-#pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (NV > 0 || q < nv) {
-          double vq[V];
-          ldv<double, V>(Vb + q * vstride + offA, vq);
-#pragma unroll
-          for (int v = 0; v < V; ++v) acc[q] += vq[v] * rA[v];
-        }
-    }
+    if constexpr (NV != 0) dots_of(rA, offA);
     if (i + 1 < cnt) {
       march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB, rB);
-      if constexpr (NV != 0) {
-        const double* Vb = Vk + boff;
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-          if (NV > 0 || q < nv) {
-            double vq[V];
-            ldv<double, V>(Vb + q * vstride + offB, vq);
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[q] += vq[v] * rB[v];
-          }
-      }
+      if constexpr (NV != 0) dots_of(rB, offB);
     }
   }
   }  // s < S

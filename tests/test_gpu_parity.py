@@ -322,6 +322,31 @@ def test_initial_guess_and_restarts():
     assert res3.converged and res3.iters == 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bf16gemm"])
+@pytest.mark.parametrize("m", [1, 2, 5, 8, 11])
+def test_solution_update_lengths(m, prec):
+    """One FGMRES cycle of exactly m iterations (the solution update then sums
+    m preconditioned vectors: the vectorised kernel up to 8, the generic one
+    beyond).  The true residual of the returned u, evaluated by the oracle,
+    must equal the cycle's least-squares residual estimate (exact in exact
+    arithmetic for flexible GMRES, whose relation A Z = V H holds for the
+    stored Z of either precision) down to a float64 rounding floor, and the
+    residual the solver reports.  alpha = 0.5 (a weaker preconditioner) keeps
+    the first iterations' residuals above that floor."""
+    announce(f"solution update m={m} {prec}")
+    params = dict(CASES["2d-tr-schur"], alpha=0.5)
+    torch, pd, prob = make(params, prec, restart=m)
+    b = np.random.default_rng(12).standard_normal((prob.nt, prob.nspace))
+    u, res = pd.solve(to_gpu(torch, b, pd.shape), rtol=1e-30, max_iter=m, restart=m)
+    assert not res.converged and res.iters == m
+    un = u.cpu().numpy().reshape(prob.nt, -1)
+    true_res = np.linalg.norm(b - ops.apply_A(prob, un)) / np.linalg.norm(b)
+    est = res.history[m]            # estimate after the m-th iteration
+    print(f"  est {est:.6e} true {true_res:.6e} reported {res.rel_resid:.6e}")
+    assert abs(true_res - est) <= 1e-7 * est + 1e-12
+    assert abs(res.rel_resid - true_res) <= 1e-9 * true_res + 1e-14
+
+
 def test_stage_timing_selection():
     announce("stage timing selection")
     torch, pd, prob = make(CASES["2d-tr-schur"], "fp32")
