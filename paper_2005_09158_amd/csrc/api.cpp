@@ -221,7 +221,7 @@ static size_t partial_chunks(const Plan& pl) {
 size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o) {
   if (!o) return 0;
   const Geom& g = pl.g;
-  size_t small = align_up(sizeof(double) * g.B * partial_chunks(pl) * MAXV) + 8 * align_up(sizeof(double) * g.B * MAXV);
+  size_t small = align_up(sizeof(double) * g.B * partial_chunks(pl) * MAXV) + 12 * align_up(sizeof(double) * g.B * MAXV);
   size_t zb = (pl.prec == Prec::F64) ? 8 : 4;
   if (o->mode == PD_MODE_FGMRES) {
     int m = std::max(1, std::min(o->restart, 32));
@@ -271,6 +271,22 @@ static void drain_timer(Plan& pl) {
     pl.timer.pool.push_back(r.b);
   }
   pl.timer.pending.clear();
+}
+
+// Removes the most recent record of `stage` (a launch that returned without
+// doing its work) and the work it was credited with.
+static void untime_last(Plan& pl, int stage, double bytes, double flops) {
+  auto& pend = pl.timer.pending;
+  for (size_t k = pend.size(); k-- > 0;) {
+    if (pend[k].stage != stage) continue;
+    hipEventSynchronize(pend[k].b);
+    pl.timer.pool.push_back(pend[k].a);
+    pl.timer.pool.push_back(pend[k].b);
+    pend.erase(pend.begin() + (ptrdiff_t)k);
+    pl.timer.bytes[stage] -= bytes;
+    pl.timer.flops[stage] -= flops;
+    return;
+  }
 }
 
 // ------------------------------------------------------------ operations
@@ -325,7 +341,7 @@ static void apply_A(Plan& pl, int variant, const void* u, bool u_f32, const doub
   const double n = (double)pl.g.NA;
   Timed t(pl, PD_STAGE_MATVEC, s, n * ((u_f32 ? 4.0 : 8.0) + 8.0 + (b ? 8.0 : 0.0)),
           n * ((pl.L == 3 ? 22.0 : 18.0) + (sq ? 2.0 : 0.0)));
-  matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s, nullptr, 0, sq ? 1 : 0, sq);
+  matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s, nullptr, 0, 0, sq, sq ? 1 : 0);
 }
 
 namespace {
@@ -339,7 +355,10 @@ struct Small {
   double* sigma;
   double* y;
   double* nrm;
+  double* giv;   // B x GIVS: Givens state for k_arnoldi_skip
+  int* skip;     // its decision
 };
+constexpr int GIVS = 3 * MAXV;   // >= 2 + 2 (restart <= 32)
 
 Small carve_small(Plan& pl, char*& p) {
   const Geom& g = pl.g;
@@ -348,6 +367,8 @@ Small carve_small(Plan& pl, char*& p) {
   double** slots[] = {&sm.h1, &sm.c1, &sm.h2, &sm.c2, &sm.sigma, &sm.y, &sm.nrm};
   for (double** q : slots) { *q = (double*)p; p += align_up(sizeof(double) * g.B * MAXV); }
   p += align_up(sizeof(double) * g.B * MAXV);
+  sm.giv = (double*)p; p += 3 * align_up(sizeof(double) * g.B * MAXV);
+  sm.skip = (int*)p; p += align_up(sizeof(double) * g.B * MAXV);
   return sm;
 }
 
@@ -359,10 +380,10 @@ static void timed_dot(Plan& pl, const double* V, int64_t vs, int nv, const doubl
   multi_dot(pl, V, vs, nv, w, part, s);
 }
 static void timed_update(Plan& pl, const double* V, int64_t vs, int nv, const double* coef, double* w,
-                         double* part, int dots, hipStream_t s) {
+                         double* part, int dots, hipStream_t s, const int* skip = nullptr) {
   const double n = (double)pl.g.NA;
   Timed t(pl, PD_STAGE_UPDATE, s, n * 8.0 * (nv + 2), n * (2.0 * nv + (dots ? 2.0 * nv + 2.0 : 0.0)));
-  update_dot(pl, V, vs, nv, coef, w, part, dots, s);
+  update_dot(pl, V, vs, nv, coef, w, part, dots, s, skip);
 }
 static void timed_reduce(Plan& pl, const double* part, int nv, const double* sigma, int nscaled,
                          double* h, double* coef, hipStream_t s, int chunks = 0) {
@@ -370,12 +391,13 @@ static void timed_reduce(Plan& pl, const double* part, int nv, const double* sig
   reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks);
 }
 namespace {
-// Pinned host staging of the solvers' small transfers: [norms | h1 h2 | sigma | y],
+// Pinned host staging of the solvers' small transfers:
+// [norms | h1 h2 | sigma | y | Givens state (3) | skip flag],
 // B * MAXV doubles each.  Pinned copies run asynchronously, so a region is
 // rewritten by the host only after a stream synchronisation that follows
 // its last copy (every Arnoldi step and every norm ends with one).
 double* pinned(Plan& pl) {
-  const size_t n = (size_t)5 * pl.g.B * MAXV;
+  const size_t n = (size_t)10 * pl.g.B * MAXV;
   if (pl.pin_n < n) {
     if (pl.pin) hipHostFree(pl.pin);
     pl.pin = nullptr;
@@ -529,6 +551,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   double* hbuf = pl.pin + (size_t)B * MAXV;
   double* sig = pl.pin + (size_t)3 * B * MAXV;
   double* yv = pl.pin + (size_t)4 * B * MAXV;
+  double* givh = pl.pin + (size_t)5 * B * MAXV;
+  int* skiph = reinterpret_cast<int*>(pl.pin + (size_t)9 * B * MAXV);
   std::vector<double> nr;
   bool first = true;
   while (true) {
@@ -555,10 +579,27 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       if (active[i]) sig[(size_t)i * MAXV] = 1.0 / nr[i];
       gv[(size_t)i * (m + 1)] = nr[i];
     }
-    hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
     std::vector<int> kk(B, 0);   // columns used per right-hand side
     std::vector<char> live = active;
-    bool second = true;
+    bool second = true, skipped = false;
+    // Givens state of step jj for k_arnoldi_skip, per right-hand side:
+    // [rtol ||b|| (negative when not live), g_jj, c_0..c_{jj-1}, s_0..s_{jj-1}],
+    // copied with the scales (the host rewrites the pinned area only after the
+    // step's synchronisation)
+    auto stage_givens = [&](int jj) {
+      for (int i = 0; i < B; ++i) {
+        double* G = givh + (size_t)i * GIVS;
+        G[0] = live[i] ? o->rtol * bn[i] : -1.0;
+        G[1] = gv[(size_t)i * (m + 1) + jj];
+        for (int q = 0; q < jj; ++q) {
+          G[2 + q] = cs[(size_t)i * m + q];
+          G[2 + jj + q] = sn[(size_t)i * m + q];
+        }
+      }
+      hipMemcpyAsync(sm.giv, givh, sizeof(double) * B * GIVS, hipMemcpyHostToDevice, s);
+    };
+    stage_givens(0);
+    hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
     int j = 0;
     for (; j < m; ++j) {
       // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a) and
@@ -571,34 +612,53 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
           const double n = (double)g.NA;
           Timed t(pl, PD_STAGE_MATVEC, s, n * ((zf32 ? 4.0 : 8.0) + 8.0 + 8.0 * (j + 1)),
                   n * ((pl.L == 3 ? 22.0 : 18.0) + 2.0 * (j + 1)));
-          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial);
+          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial, 1);
         }
-        // classical Gram-Schmidt, two passes; the first pass's dots come from the
-        // matvec kernel, the second pass's from the first pass's update kernel,
-        // the final norm by Pythagoras.  The second
-        // update is applied only when some live right-hand side keeps a
-        // component along the basis above kReorthTol of its norm after the
-        // first pass (selective reorthogonalisation): otherwise the vector is
-        // already orthogonal to that accuracy and is kept as it is.
+        // classical Gram-Schmidt, two passes; the first pass's dots (and w . w)
+        // come from the matvec kernel, the second pass's from the first pass's
+        // update kernel, the final norm by Pythagoras.  The second update is
+        // applied only when some live right-hand side keeps a component along
+        // the basis above kReorthTol of its norm after the first pass
+        // (selective reorthogonalisation): otherwise the vector is already
+        // orthogonal to that accuracy and is kept as it is.
         {
           Timed t(pl, PD_STAGE_OTHER, s);
-          reduce_partials(pl, sm.partial, j + 1, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl));
+          reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl));
         }
-        timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s);
+        // A step that ends its cycle (every live residual estimate within
+        // rtol, or the restart length or iteration limit reached) needs no
+        // orthogonalised w: its subdiagonal entry follows from w . w and the
+        // first pass by Pythagoras.  The device decides before the update,
+        // which then returns at once (the Givens state it needs was staged
+        // with the step's scales).
+        {
+          Timed t(pl, PD_STAGE_OTHER, s);
+          const bool force = j + 1 == m || iters + 1 >= o->max_iter;
+          arnoldi_skip(pl, sm.h1, sm.giv, GIVS, j, force, sm.skip, s);
+        }
+        const double upd_bytes = (double)g.NA * 8.0 * (j + 3);
+        const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
+        timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
         hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(hbuf + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
                        hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(skiph, sm.skip, sizeof(int), hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);
+        skipped = *skiph != 0;
         second = false;
-        for (int i = 0; i < B; ++i) {
-          if (!live[i]) continue;
-          const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
-          double mx = 0;
-          for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
-          if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
+        if (skipped) {
+          untime_last(pl, PD_STAGE_UPDATE, upd_bytes, upd_flops);   // it did not run
+        } else {
+          for (int i = 0; i < B; ++i) {
+            if (!live[i]) continue;
+            const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
+            double mx = 0;
+            for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
+            if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
+          }
+          if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
         }
-        if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
       }
       ++iters;
       double est_max = 0;
@@ -615,6 +675,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         double nn = h2[j + 1];
         if (second)
           for (int q = 0; q <= j; ++q) nn -= h2[q] * h2[q];
+        if (skipped) {   // w . w minus the first pass (see k_arnoldi_skip)
+          nn = h1[j + 1];
+          for (int q = 0; q <= j; ++q) nn -= h1[q] * h1[q];
+        }
         double hn = nn > 0 ? std::sqrt(nn) : 0.0;
         Hc[(size_t)j * (m + 1) + j + 1] = hn;
         if (!live[i]) { sig[(size_t)i * MAXV + j + 1] = 0.0; continue; }
@@ -645,7 +709,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         sig[(size_t)i * MAXV + j + 1] = (hn > 0 && live[i]) ? 1.0 / hn : 0.0;
       }
       push_hist(est_max);
-      if (!any_live || iters >= o->max_iter || j + 1 == m) { ++j; break; }
+      // a skipped update ends the cycle whatever the host's estimate says (w
+      // was not orthogonalised); the true residual decides what follows
+      if (skipped || !any_live || iters >= o->max_iter || j + 1 == m) { ++j; break; }
+      stage_givens(j + 1);
       hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
     }
     // solve the triangular systems and update x

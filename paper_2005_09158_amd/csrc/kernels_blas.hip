@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
                                                double c10, double c11, double c12, double c20,
                                                double c21, double c22, Stencil st, int chunk, int dir,
                                                const double* __restrict__ Vk, int64_t vstride, int nv,
-                                               double* __restrict__ partial) {
+                                               int sq, double* __restrict__ partial) {
   constexpr int NR = NV > 0 ? NV : (NV < 0 ? MAXV : 1);
   __shared__ double red[4];
   const int S = nx * ny;
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
   double acc[NR];
 #pragma unroll
   for (int i = 0; i < NR; ++i) acc[i] = 0.0;
+  double asq = 0.0;   // y . y when sq
   if (s < S) {
   const int x = s % nx, y = s / nx;
   const int64_t boff = (int64_t)bp.z * Nt * S;
@@ -164,23 +165,23 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
 #pragma unroll
     for (int v = 0; v < V; ++v) { u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = uu[v]; k1[v] = kk[v]; }
   }
-  // dots of the values r just written (at element offset off) with V_q; with
-  // NV == 1 and no V, the squared norm of the output itself
+  // dots of the values r just written (at element offset off) with V_q, and
+  // with themselves when sq
   auto dots_of = [&](const double (&r)[V], int64_t off) {
-    if (NV == 1 && Vk == nullptr) {
+    if (sq)
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[0] += r[v] * r[v];
-      return;
+      for (int v = 0; v < V; ++v) asq += r[v] * r[v];
+    if constexpr (NV != 0) {
+      const double* Vb = Vk + boff;
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (NV > 0 || q < nv) {
+          double vq[V];
+          ldv<double, V>(Vb + q * vstride + off, vq);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[q] += vq[v] * r[v];
+        }
     }
-    const double* Vb = Vk + boff;
-#pragma unroll
-    for (int q = 0; q < NR; ++q)
-      if (NV > 0 || q < nv) {
-        double vq[V];
-        ldv<double, V>(Vb + q * vstride + off, vq);
-#pragma unroll
-        for (int v = 0; v < V; ++v) acc[q] += vq[v] * r[v];
-      }
   };
   // two time steps per iteration, all of both steps' loads issued first (the
   // second step of an odd tail re-reads the first and is not stored)
@@ -199,22 +200,28 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
     }
     double rA[V], rB[V];
     march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA, rA);
-    if constexpr (NV != 0) dots_of(rA, offA);
+    dots_of(rA, offA);
     if (i + 1 < cnt) {
       march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB, rB);
-      if constexpr (NV != 0) dots_of(rB, offB);
+      dots_of(rB, offB);
     }
   }
   }  // s < S
-  if constexpr (NV != 0) {
+  if (partial != nullptr) {   // nv and sq are uniform: every thread reaches the barriers
     const int chunks = gridDim.x * gridDim.y;
     double* out = partial + ((int64_t)bp.z * chunks + bp.x + (int64_t)gridDim.x * bp.y) * MAXV;
+    const int ndots = NV > 0 ? NV : (NV < 0 ? nv : 0);
+    if constexpr (NV != 0)
 #pragma unroll
-    for (int q = 0; q < NR; ++q)
-      if (NV > 0 || q < nv) {   // nv is uniform: every thread reaches the barriers
-        const double t = block_sum(acc[q], red);
-        if (threadIdx.x == 0) out[q] = t;
-      }
+      for (int q = 0; q < NR; ++q)
+        if (q < ndots) {
+          const double t = block_sum(acc[q], red);
+          if (threadIdx.x == 0) out[q] = t;
+        }
+    if (sq) {
+      const double t = block_sum(asq, red);
+      if (threadIdx.x == 0) out[ndots] = t;
+    }
   }
 }
 
@@ -376,12 +383,14 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partia
 }
 
 // w[b] -= sum_i coef[b][i] V_i[b]; optionally partial dots of the new w with
-// V_i (slots 0..nv-1) and with itself (slot nv).
+// V_i (slots 0..nv-1) and with itself (slot nv).  Nothing happens when skip
+// is given and set (see k_arnoldi_skip).
 template <int NV, bool DOTS>
 __global__ __launch_bounds__(NT) void k_update_t(const double* __restrict__ V, int64_t vstride, int nv,
                                                  const double* __restrict__ coef, int ldc,
                                                  double* __restrict__ w, double* __restrict__ partial,
-                                                 int64_t N1, int chunks) {
+                                                 int64_t N1, int chunks, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   __shared__ double red[4];
   constexpr int NR = NV > 0 ? NV : MAXV;
   const int b = blockIdx.y, c = blockIdx.x;
@@ -487,6 +496,43 @@ __global__ __launch_bounds__(NT) void k_xupd4(const Tz* __restrict__ Z, int64_t 
   }
 }
 
+// Whether the Arnoldi step j can end its cycle without orthogonalising w.
+// h[b][q] (q <= j) are the first Gram-Schmidt pass's coefficients v_q . w and
+// h[b][j+1] = w . w, so the new subdiagonal entry is
+// sqrt(w . w - sum_q h_q^2) (Pythagoras, V orthonormal).  giv[b] holds
+// [threshold (negative: right-hand side no longer live), g_j, c_0..c_{j-1},
+// s_0..s_{j-1}]: the residual estimate so far and the cycle's Givens
+// rotations.  Rotating the new column and forming the next rotation gives the
+// least-squares residual estimate |s_j g_j| after this step.  The step skips
+// the update (flag = 1) when that subtraction is well conditioned for every
+// live right-hand side (w . w - sum h^2 above 1e-12 w . w) and either every
+// estimate is within its threshold or the host forces the end of the cycle
+// (restart length or iteration limit reached): the next basis vector is then
+// never used.  One thread: a few multiply-adds per right-hand side.
+__global__ void k_arnoldi_skip(const double* __restrict__ h, const double* __restrict__ giv, int gs,
+                               int j, int B, int force, int* __restrict__ flag) {
+  if (threadIdx.x != 0) return;
+  bool all_done = true, well = true;
+  for (int b = 0; b < B; ++b) {
+    const double* G = giv + (int64_t)b * gs;
+    const double thr = G[0];
+    if (thr < 0.0) continue;
+    const double* hc = h + (int64_t)b * MAXV;
+    const double w2 = hc[j + 1];
+    double nn = w2, cur = hc[0];
+    for (int q = 0; q <= j; ++q) nn -= hc[q] * hc[q];
+    for (int q = 0; q < j; ++q) {   // the previous rotations applied to the new column
+      const double c = G[2 + q], sn = G[2 + j + q], nx = hc[q + 1];
+      cur = -sn * cur + c * nx;
+    }
+    if (!(nn > 1e-12 * w2)) { well = false; continue; }
+    const double hn = sqrt(nn);
+    const double est = fabs(hn / hypot(cur, hn) * G[1]);
+    if (!(est <= thr)) all_done = false;
+  }
+  *flag = (well && (force || all_done)) ? 1 : 0;
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) b[e] = a[e];
 }
@@ -519,7 +565,7 @@ int matvec_chunks(const Plan& pl) {
 
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk, int64_t vstride, int nv,
-            double* partial) {
+            double* partial, int sq) {
   int V, chunk;
   const dim3 grid = matvec_grid(pl, V, chunk);
   Stencil st = stencil_of(op);
@@ -528,7 +574,7 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
 #define PD_MV(TIN, VV, K)                                                                         \
   k_matvec<TIN, VV, K><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0], \
                                            pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \
-                                           chunk, dir, Vk, vstride, nv, partial)
+                                           chunk, dir, Vk, vstride, nv, sq, partial)
 #define PD_MV_NV(TIN, VV)                                                                         \
   switch (nv) {                                                                                   \
     case 0: PD_MV(TIN, VV, 0); break;                                                             \
@@ -592,21 +638,26 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
 }
 
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
-                double* w, double* partial, int want_dots, hipStream_t s) {
+                double* w, double* partial, int want_dots, hipStream_t s, const int* skip) {
   int chunks = dot_chunks(pl);
   dim3 grid(chunks, pl.g.B);
 #define PD_UP(K)                                                                                  \
   case K:                                                                                         \
-    if (want_dots) k_update_t<K, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks); \
-    else k_update_t<K, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks); \
+    if (want_dots) k_update_t<K, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip); \
+    else k_update_t<K, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip); \
     return;
   switch (nv) {
     PD_UP(1) PD_UP(2) PD_UP(3) PD_UP(4) PD_UP(5) PD_UP(6) PD_UP(7) PD_UP(8)
     default:
-      if (want_dots) k_update_t<0, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks);
-      else k_update_t<0, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks);
+      if (want_dots) k_update_t<0, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip);
+      else k_update_t<0, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip);
   }
 #undef PD_UP
+}
+
+void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, int j, bool force,
+                  int* flag, hipStream_t s) {
+  k_arnoldi_skip<<<1, 64, 0, s>>>(h, giv, gs, j, pl.g.B, force ? 1 : 0, flag);
 }
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
