@@ -58,6 +58,13 @@ template <typename T> struct V4;
 template <> struct V4<float> { using t = float4; };
 template <> struct V4<double> { using t = double4; };
 
+// Load unit of the pipelined kernel's pivot staging: four values where the
+// pivot blocks are 16-byte aligned (sx % 4 == 0), else two.
+template <typename T, bool VEC> struct PivUnit {
+  static constexpr int n = VEC ? 4 : 2;
+  typedef T t __attribute__((ext_vector_type(VEC ? 4 : 2)));
+};
+
 // Coupling product with fragments loaded straight from global memory
 // (sx % 4 == 0).  Within each block of 16 consecutive solved modes j, lane
 // group g = lane/16 owns j0 + 4g .. j0 + 4g + 3 and feeds element s of its
@@ -379,6 +386,33 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
   // wave 0's copy of the block it solved last: value i of line q of lane l at
   // (q R + i) 64 + l (conflict-free), read back by the next step's near coupling
   Cx<T>* wsol = reinterpret_cast<Cx<T>*>(tns + 4 * NB * NB);
+  // inverse pivots of the block being solved: row y = p R + i of line q at
+  // (q R + i) P + p, so that wave 0's lanes read consecutive entries
+  Cx<T>* pivs = wsol + NB * R * 64;
+  // The coupling waves load the next block's pivots from global memory at the
+  // start of a step (their latency hidden behind the step) and store them here
+  // at the start of the following one, after wave 0 has finished with the
+  // previous block's: the solves never wait on HBM for them.  Lines of up to
+  // 256 rows (beyond, the registers are taken: wave 0 loads them itself, one
+  // line ahead).
+  constexpr bool PIVL = R * P <= 256;
+  using PV = typename PivUnit<T, VEC>::t;
+  constexpr int PVW = PivUnit<T, VEC>::n;                        // T per unit
+  constexpr int PU = PIVL ? (2 * NB * R * P / PVW + SWT - 64 - 1) / (SWT - 64) : 1;   // units per coupling thread
+  PV pv[PU];
+  auto piv_store = [&](int ct, int nunits) {   // pv (units ct + u (SWT - 64)) -> pivs
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int e = ct + u * (SWT - 64);
+      if (e < nunits)
+#pragma unroll
+        for (int h = 0; h < PVW / 2; ++h) {
+          const int c = e * (PVW / 2) + h;   // complex index q sy + y in the block
+          const int q = c / sy, y = c - q * sy;
+          pivs[(q * R + y % R) * P + y / R] = Cx<T>{pv[u][2 * h], pv[u][2 * h + 1]};
+        }
+    }
+  };
 
   const int n = blockIdx.x, b = blockIdx.y;
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
@@ -420,10 +454,17 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
   };
 
+  const T* lun = lu + (int64_t)n * sx * sy * 2;
   {  // prologue: the last block (the only one that may be partial)
     const int k0 = (nblk - 1) * NB, nk = sx - k0;
     tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
     stage_coef(tbs, k0, k0, nk, true, (int)threadIdx.x, SWT);
+    if constexpr (PIVL)
+      for (int c = threadIdx.x; c < nk * sy; c += SWT) {
+        const int q = c / sy, y = c - q * sy;
+        const T* src = lun + ((int64_t)k0 * sy + c) * 2;
+        pivs[(q * R + y % R) * P + y / R] = Cx<T>{src[0], src[1]};
+      }
   }
   __syncthreads();
 
@@ -444,8 +485,10 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       const int k0p = k0 + NB, nkp = min(NB, sx - k0p);
       if (VEC && nkp == NB) tile_store_vec<T, NB, R * P>(slice, nre, nim, k0p, sx, sy, ldy, R, tid, SWT);
       else tile_store_by(slice, nre, nim, k0p, nkp, NB, sx, sy, ldy, R, tid, SWT);
+      // block kb's pivots, loaded by the coupling waves in the previous step
+      if (PIVL && tid >= 64) piv_store(tid - 64, 2 * NB * sy / PVW);
     }
-    __syncthreads();   // block kb+1 in global memory; its LDS buffer is free
+    __syncthreads();   // block kb+1 in global memory; its LDS buffer is free; block kb's pivots staged
     const int k0n = k0 - NB;   // next block (always full) when kb > 0
     const bool far = ((st + phase) & 1) == 0;
     // Rows [y0, y1) of block kb-1: staged into the LDS buffer, coupled to every
@@ -531,11 +574,17 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       const Cx<T> cc = active ? Cx<T>{(T)(l2.x * up), (T)(l2.y * up)} : cz<T>();
       const Cx<T>* tbc = reinterpret_cast<const Cx<T>*>(tbs + cur * 2 * NB * NB);
       const Cx<T>* tnc = reinterpret_cast<const Cx<T>*>(tns + cur * 2 * NB * NB);
-      const T* lun = lu + (int64_t)n * sx * sy * 2;
-      // inverse pivots: read once, so loaded non-temporally (they should not
-      // push the solved lines, which the coupling product re-reads, out of
-      // the last-level cache)
+      // inverse pivots of line q (one beyond the line's rows): from LDS, or
+      // read once from global memory, non-temporally (they should not push
+      // the solved lines, which the coupling product re-reads, out of the
+      // last-level cache)
       auto load_inv = [&](int q, Cx<T> (&iv)[R]) {
+        if constexpr (PIVL) {
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            iv[i] = (active && p * R + i < sy) ? pivs[(q * R + i) * P + p] : c1<T>();
+          return;
+        }
         const T* src = lun + ((int64_t)(k0 + q) * sy + p * R) * 2;
         if constexpr (sizeof(T) == 4 && R % 2 == 0) {
           typedef float f4v __attribute__((ext_vector_type(4)));
@@ -625,6 +674,15 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       // coefficients of block kb-1 (inside it; towards block kb): loads
       // issued now, their latency hidden behind the tile and the products
       static_assert(NB * NB <= SWT - 64, "one coefficient per thread");
+      if constexpr (PIVL) {  // block kb-1's pivots: contiguous in global memory (one unit per PVW values)
+        const PV* src = reinterpret_cast<const PV*>(lun + (int64_t)k0n * sy * 2);
+        const int nunits = 2 * NB * sy / PVW;
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          const int e = ct + u * (SWT - 64);
+          if (e < nunits) pv[u] = __builtin_nontemporal_load(src + e);
+        }
+      }
       T cbr = 0, cbi = 0, cnr = 0, cni = 0;
       if (ct < NB * NB) {
         const int qa = ct / NB, qb = ct - qa * NB;
@@ -937,7 +995,9 @@ void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
 template <typename T, int NB>
 size_t piped_lds(const SweepShape& sh) {
   // two tiles, two pairs of coefficient blocks, wave 0's solution copy
-  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64);
+  // + the pivots of one block (lines of up to 256 rows)
+  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64 +
+                      (sh.R * sh.P <= 256 ? (size_t)2 * NB * sh.R * sh.P : 0));
 }
 
 template <typename T, int R, int P, int NB, int RB, int W0B>
