@@ -380,10 +380,11 @@ static void timed_dot(Plan& pl, const double* V, int64_t vs, int nv, const doubl
   multi_dot(pl, V, vs, nv, w, part, s);
 }
 static void timed_update(Plan& pl, const double* V, int64_t vs, int nv, const double* coef, double* w,
-                         double* part, int dots, hipStream_t s, const int* skip = nullptr) {
+                         double* part, int dots, hipStream_t s, const int* skip = nullptr,
+                         const double* V0 = nullptr) {
   const double n = (double)pl.g.NA;
   Timed t(pl, PD_STAGE_UPDATE, s, n * 8.0 * (nv + 2), n * (2.0 * nv + (dots ? 2.0 * nv + 2.0 : 0.0)));
-  update_dot(pl, V, vs, nv, coef, w, part, dots, s, skip);
+  update_dot(pl, V, vs, nv, coef, w, part, dots, s, skip, V0);
 }
 static void timed_reduce(Plan& pl, const double* part, int nv, const double* sigma, int nscaled,
                          double* h, double* coef, hipStream_t s, int chunks = 0) {
@@ -450,15 +451,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   const size_t zb = zf32 ? 4 : 8;
   Small sm = carve_small(pl, p);
   if (!pinned(pl)) { set_error("pinned host staging allocation failed"); return PD_ERR_HIP; }
-  // FGMRES from a zero guess takes V_0 = b: copy and norm in one pass
+  // FGMRES from a zero guess takes V_0 = b: the first cycle reads it in place
   const bool fused_start = o->mode == PD_MODE_FGMRES && !o->use_x0;
   std::vector<double> bn;
-  if (fused_start) {
-    Timed t(pl, PD_STAGE_OTHER, s, 16.0 * g.NA, 2.0 * g.NA);
-    copy_sq(pl, b, (double*)p, sm.partial, s);
-  } else {
-    timed_dot(pl, b, 0, 1, b, sm.partial, s);
-  }
+  timed_dot(pl, b, 0, 1, b, sm.partial, s);
   norms_from(pl, sm, bn, s);
   for (int i = 0; i < B; ++i)
     if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
@@ -557,9 +553,12 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   bool first = true;
   while (true) {
     // residual of the current iterate into V_0 (from a zero guess V_0 = b,
-    // copied with its norm at the start)
+    // read where it is: V0x, in place of the basis slot, for the kernels that
+    // read V_0)
+    const double* V0x = nullptr;
     if (first && fused_start) {
       nr = bn;
+      V0x = b;
     } else {
       if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
       apply_A(pl, variant, u, false, b, Vj(0), s, sm.partial);
@@ -604,7 +603,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     for (; j < m; ++j) {
       // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a) and
       // read from the device copy of the scales, entry i * MAXV + j)
-      apply_prec(pl, variant, Vj(j), sm.sigma + j, MAXV, Zj(j), zf32, 0, s);
+      apply_prec(pl, variant, (j == 0 && V0x) ? V0x : Vj(j), sm.sigma + j, MAXV, Zj(j), zf32, 0, s);
       {
         double* w = Vj(j + 1);
         // w = A z_j with the first pass's dots V_q . w (q <= j) from the same kernel
@@ -612,7 +611,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
           const double n = (double)g.NA;
           Timed t(pl, PD_STAGE_MATVEC, s, n * ((zf32 ? 4.0 : 8.0) + 8.0 + 8.0 * (j + 1)),
                   n * ((pl.L == 3 ? 22.0 : 18.0) + 2.0 * (j + 1)));
-          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial, 1);
+          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial, 1, V0x);
         }
         // classical Gram-Schmidt, two passes; the first pass's dots (and w . w)
         // come from the matvec kernel, the second pass's from the first pass's
@@ -638,7 +637,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         }
         const double upd_bytes = (double)g.NA * 8.0 * (j + 3);
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
-        timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip);
+        timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip, V0x);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
         hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
         hipMemcpyAsync(hbuf + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
@@ -657,7 +656,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
             for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
             if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
           }
-          if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s);
+          if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s, nullptr, V0x);
         }
       }
       ++iters;

@@ -145,12 +145,13 @@ size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu
 // all-at-once operator
 // y = A u (or b - A u).  With nv > 0 also the partial dots of y with the
-// vectors Vk + i vstride (i < nv), and with sq the partial sums of y . y
-// (slot nv), one per workgroup (matvec_chunks per right-hand side, layout as
-// multi_dot's partial sums).
+// vectors Vk + i vstride (i < nv; vector 0 at V0 instead when V0 is given),
+// and with sq the partial sums of y . y (slot nv), one per workgroup
+// (matvec_chunks per right-hand side, layout as multi_dot's partial sums).
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk = nullptr,
-            int64_t vstride = 0, int nv = 0, double* partial = nullptr, int sq = 0);
+            int64_t vstride = 0, int nv = 0, double* partial = nullptr, int sq = 0,
+            const double* V0 = nullptr);
 int matvec_chunks(const Plan& pl);
 void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,
                hipStream_t s);
@@ -166,11 +167,12 @@ void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const d
 // chunks: partial sums per right-hand side (<= 0: dot_chunks).
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
                      int nscaled, double* h, double* coef, hipStream_t s, int chunks = 0);
-// w -= sum_i coef_i V_i (i < nv), with the partial dots of the result when
-// want_dots; a no-op when skip is given and *skip is set on the device.
+// w -= sum_i coef_i V_i (i < nv; V_0 at V0 instead when V0 is given), with
+// the partial dots of the result when want_dots; a no-op when skip is given
+// and *skip is set on the device.
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
                 double* w, double* partial, int want_dots, hipStream_t s,
-                const int* skip = nullptr);
+                const int* skip = nullptr, const double* V0 = nullptr);
 // Device-side test whether Arnoldi step j ends its cycle without the update
 // (*flag = 1): h = first-pass coefficients plus w . w in slot j+1, giv = per
 // right-hand side [threshold, g_j, c_0..c_{j-1}, s_0..s_{j-1}] with stride gs.
@@ -178,8 +180,6 @@ void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, in
                   int* flag, hipStream_t s);
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
               const double* y, double* x, bool overwrite, hipStream_t s);
-// dst = src per right-hand side, partial sums of src^2 into slot 0 (see multi_dot)
-void copy_sq(const Plan& pl, const double* src, double* dst, double* partial, hipStream_t s);
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);
 void fill_zero(double* dst, int64_t n, hipStream_t s);
 

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
                                                double c10, double c11, double c12, double c20,
                                                double c21, double c22, Stencil st, int chunk, int dir,
                                                const double* __restrict__ Vk, int64_t vstride, int nv,
-                                               int sq, double* __restrict__ partial) {
+                                               int sq, double* __restrict__ partial,
+                                               const double* __restrict__ V0) {
   constexpr int NR = NV > 0 ? NV : (NV < 0 ? MAXV : 1);
   __shared__ double red[4];
   const int S = nx * ny;
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
       for (int q = 0; q < NR; ++q)
         if (NV > 0 || q < nv) {
           double vq[V];
-          ldv<double, V>(Vb + q * vstride + off, vq);
+          ldv<double, V>(((q == 0 && V0 != nullptr) ? V0 + boff : Vb + q * vstride) + off, vq);
 #pragma unroll
           for (int v = 0; v < V; ++v) acc[q] += vq[v] * r[v];
         }
@@ -344,26 +345,6 @@ __global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int
   }
 }
 
-// dst[b] = src[b] and partial[b][chunk][0] = sum over the chunk of src^2:
-// the first Krylov vector and its norm from one read of the right-hand side.
-__global__ __launch_bounds__(NT) void k_copy_sq(const double* __restrict__ src, double* __restrict__ dst,
-                                                double* __restrict__ partial, int64_t N1, int chunks) {
-  __shared__ double red[4];
-  const int b = blockIdx.y, c = blockIdx.x;
-  const int64_t per = ((N1 + chunks - 1) / chunks + 1) & ~(int64_t)1;
-  const int64_t beg = c * per, end = min(N1, beg + per);
-  const double* sb = src + (int64_t)b * N1;
-  double* db = dst + (int64_t)b * N1;
-  double acc = 0;
-  for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
-    const double2 v = *reinterpret_cast<const double2*>(sb + e);
-    *reinterpret_cast<double2*>(db + e) = v;
-    acc += v.x * v.x + v.y * v.y;
-  }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[((int64_t)b * chunks + c) * MAXV] = t;
-}
-
 // t = sum_c partial[b][c][i]; with the Krylov scale s = sigma[b][i] (1 for
 // i >= nscaled or sigma == null): h[b][i] = t s and coef[b][i] = t s^2.
 __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partial, int nv, int chunks,
@@ -389,7 +370,8 @@ template <int NV, bool DOTS>
 __global__ __launch_bounds__(NT) void k_update_t(const double* __restrict__ V, int64_t vstride, int nv,
                                                  const double* __restrict__ coef, int ldc,
                                                  double* __restrict__ w, double* __restrict__ partial,
-                                                 int64_t N1, int chunks, const int* __restrict__ skip) {
+                                                 int64_t N1, int chunks, const int* __restrict__ skip,
+                                                 const double* __restrict__ V0) {
   if (skip != nullptr && *skip != 0) return;
   __shared__ double red[4];
   constexpr int NR = NV > 0 ? NV : MAXV;
@@ -410,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_update_t(const double* __restrict__ V, i
 #pragma unroll
     for (int i = 0; i < NR; ++i)
       if (NV > 0 || i < nv) {
-        vv[i] = *reinterpret_cast<const double2*>(Vb + i * vstride + e);
+        vv[i] = *reinterpret_cast<const double2*>(((i == 0 && V0 != nullptr) ? V0 + (int64_t)b * N1 : Vb + i * vstride) + e);
         wv.x -= cf[i] * vv[i].x;
         wv.y -= cf[i] * vv[i].y;
       }
@@ -565,7 +547,7 @@ int matvec_chunks(const Plan& pl) {
 
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk, int64_t vstride, int nv,
-            double* partial, int sq) {
+            double* partial, int sq, const double* V0) {
   int V, chunk;
   const dim3 grid = matvec_grid(pl, V, chunk);
   Stencil st = stencil_of(op);
@@ -574,7 +556,7 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
 #define PD_MV(TIN, VV, K)                                                                         \
   k_matvec<TIN, VV, K><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0], \
                                            pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \
-                                           chunk, dir, Vk, vstride, nv, sq, partial)
+                                           chunk, dir, Vk, vstride, nv, sq, partial, V0)
 #define PD_MV_NV(TIN, VV)                                                                         \
   switch (nv) {                                                                                   \
     case 0: PD_MV(TIN, VV, 0); break;                                                             \
@@ -638,19 +620,20 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
 }
 
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
-                double* w, double* partial, int want_dots, hipStream_t s, const int* skip) {
+                double* w, double* partial, int want_dots, hipStream_t s, const int* skip,
+                const double* V0) {
   int chunks = dot_chunks(pl);
   dim3 grid(chunks, pl.g.B);
 #define PD_UP(K)                                                                                  \
   case K:                                                                                         \
-    if (want_dots) k_update_t<K, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip); \
-    else k_update_t<K, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip); \
+    if (want_dots) k_update_t<K, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip, V0); \
+    else k_update_t<K, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip, V0); \
     return;
   switch (nv) {
     PD_UP(1) PD_UP(2) PD_UP(3) PD_UP(4) PD_UP(5) PD_UP(6) PD_UP(7) PD_UP(8)
     default:
-      if (want_dots) k_update_t<0, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip);
-      else k_update_t<0, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip);
+      if (want_dots) k_update_t<0, true><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip, V0);
+      else k_update_t<0, false><<<grid, NT, 0, s>>>(V, vstride, nv, coef, MAXV, w, partial, pl.g.N1, chunks, skip, V0);
   }
 #undef PD_UP
 }
@@ -680,11 +663,6 @@ void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int
     k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
   else
     k_xupd<double><<<grid, NT, 0, s>>>((const double*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
-}
-
-void copy_sq(const Plan& pl, const double* src, double* dst, double* partial, hipStream_t s) {
-  int chunks = dot_chunks(pl);
-  k_copy_sq<<<dim3(chunks, pl.g.B), NT, 0, s>>>(src, dst, partial, pl.g.N1, chunks);
 }
 
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s) {
