@@ -16,9 +16,13 @@ namespace pd {
 namespace {
 thread_local std::string g_last_error;
 constexpr int MAXV = 33;   // Krylov slots per right-hand side (restart <= 32)
-// Largest component along the Krylov basis, relative to the vector's norm,
-// that the first Gram-Schmidt pass may leave without a second pass.
-constexpr double kReorthTol = 1e-12;
+// Second Gram-Schmidt pass (see the Arnoldi step): components along the
+// Krylov basis left by the first pass, relative to the vector's norm (eta),
+// never need it below kReorthTol and always do above kReorthMax; in between
+// they do when eta times the residual estimate before the step exceeds
+// kReorthRel rtol (the error a skipped pass leaves in the residual estimate
+// is about that product).
+constexpr double kReorthTol = 1e-12, kReorthMax = 1e-6, kReorthRel = 1e-2;
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -617,9 +621,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         // come from the matvec kernel, the second pass's from the first pass's
         // update kernel, the final norm by Pythagoras.  The second update is
         // applied only when some live right-hand side keeps a component along
-        // the basis above kReorthTol of its norm after the first pass
-        // (selective reorthogonalisation): otherwise the vector is already
-        // orthogonal to that accuracy and is kept as it is.
+        // the basis that matters (kReorthTol, kReorthMax, kReorthRel):
+        // otherwise the vector is kept as it is.
         {
           Timed t(pl, PD_STAGE_OTHER, s);
           reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl));
@@ -654,7 +657,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
             const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
             double mx = 0;
             for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
-            if (!(mx <= kReorthTol * kReorthTol * h2[j + 1])) second = true;
+            const double eta = std::sqrt(mx / h2[j + 1]);   // NaN when h2[j+1] <= 0: second pass
+            const double est_prev = std::fabs(gv[(size_t)i * (m + 1) + j]) / bn[i];
+            if (!(eta <= kReorthTol) && (!(eta <= kReorthMax) || !(eta * est_prev <= kReorthRel * o->rtol)))
+              second = true;
           }
           if (second) timed_update(pl, V, vs, j + 1, sm.c2, w, sm.partial, 0, s, nullptr, V0x);
         }
