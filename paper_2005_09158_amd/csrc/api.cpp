@@ -368,11 +368,21 @@ Small carve_small(Plan& pl, char*& p) {
   const Geom& g = pl.g;
   Small sm;
   sm.partial = (double*)p; p += align_up(sizeof(double) * g.B * partial_chunks(pl) * MAXV);
-  double** slots[] = {&sm.h1, &sm.c1, &sm.h2, &sm.c2, &sm.sigma, &sm.y, &sm.nrm};
-  for (double** q : slots) { *q = (double*)p; p += align_up(sizeof(double) * g.B * MAXV); }
-  p += align_up(sizeof(double) * g.B * MAXV);
-  sm.giv = (double*)p; p += 3 * align_up(sizeof(double) * g.B * MAXV);
-  sm.skip = (int*)p; p += align_up(sizeof(double) * g.B * MAXV);
+  // slots of B * MAXV doubles (rounded up to ALIGN); h1, h2 and the skip flag
+  // are adjacent (one copy to the host per Arnoldi step), and so are sigma and
+  // the Givens state (one copy to the device)
+  const size_t slot = align_up(sizeof(double) * g.B * MAXV);
+  auto take = [&](size_t nslots) { double* q = (double*)p; p += nslots * slot; return q; };
+  sm.h1 = take(1);
+  sm.h2 = take(1);
+  sm.skip = (int*)take(1);
+  sm.c1 = take(1);
+  sm.c2 = take(1);
+  sm.sigma = take(1);
+  sm.giv = take(3);
+  sm.y = take(1);
+  sm.nrm = take(1);
+  take(1);
   return sm;
 }
 
@@ -396,13 +406,16 @@ static void timed_reduce(Plan& pl, const double* part, int nv, const double* sig
   reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks);
 }
 namespace {
-// Pinned host staging of the solvers' small transfers:
-// [norms | h1 h2 | sigma | y | Givens state (3) | skip flag],
+// Pinned host staging of the solvers' small transfers, in slots laid out like
+// the device's (pin_slot doubles each): [norms | h1 h2 skip | sigma Givens
+// state (3) | y],
 // B * MAXV doubles each.  Pinned copies run asynchronously, so a region is
 // rewritten by the host only after a stream synchronisation that follows
 // its last copy (every Arnoldi step and every norm ends with one).
+size_t pin_slot(const Plan& pl) { return align_up(sizeof(double) * pl.g.B * MAXV) / sizeof(double); }
+
 double* pinned(Plan& pl) {
-  const size_t n = (size_t)10 * pl.g.B * MAXV;
+  const size_t n = 9 * pin_slot(pl);
   if (pl.pin_n < n) {
     if (pl.pin) hipHostFree(pl.pin);
     pl.pin = nullptr;
@@ -548,11 +561,13 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   std::vector<double> H((size_t)B * (m + 1) * m), gv((size_t)B * (m + 1)), cs((size_t)B * m),
       sn((size_t)B * m);
   // pinned staging (see pinned): Hessenberg columns, Krylov scales, LSQ solution
-  double* hbuf = pl.pin + (size_t)B * MAXV;
-  double* sig = pl.pin + (size_t)3 * B * MAXV;
-  double* yv = pl.pin + (size_t)4 * B * MAXV;
-  double* givh = pl.pin + (size_t)5 * B * MAXV;
-  int* skiph = reinterpret_cast<int*>(pl.pin + (size_t)9 * B * MAXV);
+  const size_t ps = pin_slot(pl);
+  double* hbuf = pl.pin + ps;            // h1, then h2 at + ps, then the skip flag
+  double* h2buf = hbuf + ps;
+  int* skiph = reinterpret_cast<int*>(hbuf + 2 * ps);
+  double* sig = pl.pin + 4 * ps;         // sigma, then the Givens state at + ps
+  double* givh = sig + ps;
+  double* yv = pl.pin + 8 * ps;
   std::vector<double> nr;
   bool first = true;
   while (true) {
@@ -599,10 +614,13 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
           G[2 + jj + q] = sn[(size_t)i * m + q];
         }
       }
-      hipMemcpyAsync(sm.giv, givh, sizeof(double) * B * GIVS, hipMemcpyHostToDevice, s);
+    };
+    // the step's scales and Givens state, one copy
+    auto send_scales = [&]() {
+      hipMemcpyAsync(sm.sigma, sig, sizeof(double) * (ps + (size_t)B * GIVS), hipMemcpyHostToDevice, s);
     };
     stage_givens(0);
-    hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
+    send_scales();
     int j = 0;
     for (; j < m; ++j) {
       // z_j = P^{-1} v_j  (v_j = sigma_j V_j, the scale fused into Step-(a) and
@@ -642,10 +660,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip, V0x);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
-        hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * B * MAXV, hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(hbuf + (size_t)B * MAXV, sm.h2, sizeof(double) * B * MAXV,
-                       hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(skiph, sm.skip, sizeof(int), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * 2 * ps + sizeof(int), hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);
         skipped = *skiph != 0;
         second = false;
@@ -654,7 +669,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         } else {
           for (int i = 0; i < B; ++i) {
             if (!live[i]) continue;
-            const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
+            const double* h2 = h2buf + (size_t)i * MAXV;
             double mx = 0;
             for (int q = 0; q <= j; ++q) mx = std::max(mx, h2[q] * h2[q]);
             const double eta = std::sqrt(mx / h2[j + 1]);   // NaN when h2[j+1] <= 0: second pass
@@ -670,7 +685,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       bool any_live = false;
       for (int i = 0; i < B; ++i) {
         const double* h1 = hbuf + (size_t)i * MAXV;
-        const double* h2 = hbuf + (size_t)B * MAXV + (size_t)i * MAXV;
+        const double* h2 = h2buf + (size_t)i * MAXV;
         double* Hc = H.data() + (size_t)i * (m + 1) * m;   // column-major (m+1) x m
         for (int q = 0; q <= j; ++q) {
           double v = h1[q] + (second ? h2[q] : 0.0);
@@ -718,7 +733,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       // was not orthogonalised); the true residual decides what follows
       if (skipped || !any_live || iters >= o->max_iter || j + 1 == m) { ++j; break; }
       stage_givens(j + 1);
-      hipMemcpyAsync(sm.sigma, sig, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
+      send_scales();
     }
     // solve the triangular systems and update x
     std::fill(yv, yv + (size_t)B * MAXV, 0.0);
