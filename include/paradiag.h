@@ -165,7 +165,8 @@ paradiag_status paradiag_apply_precond(paradiag_plan plan, const double* r, doub
 
 /* Solve A u = b per opts->mode.  u: in = initial guess if opts->use_x0,
  * out = solution.  Returns PD_NOT_CONVERGED (u = last iterate) when max_iter
- * is reached first. */
+ * is reached first.  b is read throughout the solve (from a zero guess the
+ * first Krylov vector is b itself); u overlapping b is PD_ERR_INVALID. */
 paradiag_status paradiag_solve(paradiag_plan plan, const double* b, double* u,
                                const paradiag_solve_opts* opts, paradiag_solve_info* info,
                                void* stream);
