@@ -362,7 +362,7 @@ struct Small {
   double* giv;   // B x GIVS: Givens state for k_arnoldi_skip
   int* skip;     // its decision
 };
-constexpr int GIVS = 3 * MAXV;   // >= 2 + 2 (restart <= 32)
+constexpr int GIVS = 3 * MAXV;   // per right-hand side: >= 2 + 2 (m - 1) entries for restart m <= 32
 
 Small carve_small(Plan& pl, char*& p) {
   const Geom& g = pl.g;
@@ -406,12 +406,11 @@ static void timed_reduce(Plan& pl, const double* part, int nv, const double* sig
   reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks);
 }
 namespace {
-// Pinned host staging of the solvers' small transfers, in slots laid out like
-// the device's (pin_slot doubles each): [norms | h1 h2 skip | sigma Givens
-// state (3) | y],
-// B * MAXV doubles each.  Pinned copies run asynchronously, so a region is
-// rewritten by the host only after a stream synchronisation that follows
-// its last copy (every Arnoldi step and every norm ends with one).
+// Pinned host staging of the solvers' small transfers, in slots of pin_slot
+// doubles laid out like the device's: [norms | h1 h2 skip | sigma, Givens
+// state (3 slots) | y].  Pinned copies run asynchronously, so a region is
+// rewritten by the host only after a stream synchronisation that follows its
+// last copy (every Arnoldi step and every norm ends with one).
 size_t pin_slot(const Plan& pl) { return align_up(sizeof(double) * pl.g.B * MAXV) / sizeof(double); }
 
 double* pinned(Plan& pl) {
