@@ -231,7 +231,8 @@ size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o) {
     int m = std::max(1, std::min(o->restart, 32));
     return small + align_up(sizeof(double) * (size_t)g.NA) * (m + 1) + align_up(zb * (size_t)g.NA) * m;
   }
-  // stationary: the residual vector; direct: the residual it reports
+  // stationary: the residual vector; direct: only the norm of its residual
+  if (o->mode == PD_MODE_DIRECT) return small;
   return small + align_up(sizeof(double) * (size_t)g.NA);
 }
 
@@ -339,11 +340,11 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
 }
 
 // y = b - A u (A u without b); with `sq`, also the partial sums of y . y, one
-// per matvec workgroup (reduced with matvec_chunks)
+// per matvec workgroup (reduced with matvec_chunks); y null: the norm only
 static void apply_A(Plan& pl, int variant, const void* u, bool u_f32, const double* b, double* y,
                     hipStream_t s, double* sq = nullptr) {
   const double n = (double)pl.g.NA;
-  Timed t(pl, PD_STAGE_MATVEC, s, n * ((u_f32 ? 4.0 : 8.0) + 8.0 + (b ? 8.0 : 0.0)),
+  Timed t(pl, PD_STAGE_MATVEC, s, n * ((u_f32 ? 4.0 : 8.0) + (y ? 8.0 : 0.0) + (b ? 8.0 : 0.0)),
           n * ((pl.L == 3 ? 22.0 : 18.0) + (sq ? 2.0 : 0.0)));
   matvec(pl, pl.op[variant], u, u_f32, b, y, variant, s, nullptr, 0, 0, sq, sq ? 1 : 0);
 }
@@ -516,10 +517,10 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     apply_prec(pl, variant, b, nullptr, 0, u, false, 0, s);
     iters = 1;
     for (int i = 0; i < B; ++i) it_rhs[i] = 1;
-    // residual of the result with respect to A (reported, not iterated)
+    // residual of the result with respect to A (reported, not iterated; its
+    // norm only)
     std::vector<double> nr;
-    double* rv = (double*)p;
-    apply_A(pl, variant, u, false, b, rv, s, sm.partial);
+    apply_A(pl, variant, u, false, b, nullptr, s, sm.partial);
     norms_from(pl, sm, nr, s, matvec_chunks(pl));
     rel(nr);
     push_hist(*std::max_element(res.begin(), res.end()));
@@ -578,10 +579,13 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       nr = bn;
       V0x = b;
     } else {
+      // the norm first; the residual itself is stored (as V_0) only when
+      // another cycle follows
       if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
-      apply_A(pl, variant, u, false, b, Vj(0), s, sm.partial);
+      apply_A(pl, variant, u, false, b, nullptr, s, sm.partial);
       norms_from(pl, sm, nr, s, matvec_chunks(pl));
     }
+    const bool restart_cycle = !(first && fused_start);
     first = false;
     bool all = rel(nr);
     for (int i = 0; i < B; ++i)
@@ -589,6 +593,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     push_hist(*std::max_element(res.begin(), res.end()));
     if (all) return finish(true);
     if (iters >= o->max_iter) return finish(false);
+    if (restart_cycle) apply_A(pl, variant, u, false, b, Vj(0), s);
     std::vector<char> active(B);
     for (int i = 0; i < B; ++i) active[i] = res[i] > o->rtol && nr[i] > 0;
     std::fill(sig, sig + (size_t)B * MAXV, 0.0);

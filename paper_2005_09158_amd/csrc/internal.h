@@ -148,6 +148,7 @@ void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills 
 // vectors Vk + i vstride (i < nv; vector 0 at V0 instead when V0 is given),
 // and with sq the partial sums of y . y (slot nv), one per workgroup
 // (matvec_chunks per right-hand side, layout as multi_dot's partial sums).
+// y may be null with sq: only the norm is formed.
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk = nullptr,
             int64_t vstride = 0, int nv = 0, double* partial = nullptr, int sq = 0,

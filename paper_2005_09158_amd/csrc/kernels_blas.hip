@@ -113,6 +113,7 @@ __device__ __forceinline__ void march_step(const double (&u0)[V], const double (
     if (hasb) r[v] = bv[v] - r[v];
     u2[v] = u1[v]; k2[v] = k1[v]; u1[v] = u0[v]; k1[v] = k0[v];
   }
+  if (dst == nullptr) return;   // only the values (for their norm) are wanted
   if constexpr (V == 1) {
     dst[0] = r[0];
   } else {
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
   const int x = s % nx, y = s / nx;
   const int64_t boff = (int64_t)bp.z * Nt * S;
   const Tin* ub = u + boff;
-  double* yb = yv + boff;
+  double* yb = yv ? yv + boff : nullptr;   // null: y is not stored (sq only)
   const double* bb = b ? b + boff : nullptr;
   const int nbeg = bp.y * chunk;
   const int nend = min(Nt, nbeg + chunk);
@@ -200,10 +201,10 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
       ldv<double, V>(bb + offB, bB);
     }
     double rA[V], rB[V];
-    march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offA, rA);
+    march_step<V>(uA, kA, bA, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb ? yb + offA : nullptr, rA);
     dots_of(rA, offA);
     if (i + 1 < cnt) {
-      march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb + offB, rB);
+      march_step<V>(uB, kB, bB, bb != nullptr, L, c10, c11, c12, c20, c21, c22, u1, k1, u2, k2, yb ? yb + offB : nullptr, rB);
       dots_of(rB, offB);
     }
   }
