@@ -402,16 +402,20 @@ static void timed_update(Plan& pl, const double* V, int64_t vs, int nv, const do
   update_dot(pl, V, vs, nv, coef, w, part, dots, s, skip, V0);
 }
 static void timed_reduce(Plan& pl, const double* part, int nv, const double* sigma, int nscaled,
-                         double* h, double* coef, hipStream_t s, int chunks = 0) {
+                         double* h, double* coef, hipStream_t s, int chunks = 0,
+                         double* hhost = nullptr) {
   Timed t(pl, PD_STAGE_OTHER, s);
-  reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks);
+  reduce_partials(pl, part, nv, sigma, nscaled, h, coef, s, chunks, hhost);
 }
 namespace {
-// Pinned host staging of the solvers' small transfers, in slots of pin_slot
-// doubles laid out like the device's: [norms | h1 h2 skip | sigma, Givens
-// state (3 slots) | y].  Pinned copies run asynchronously, so a region is
-// rewritten by the host only after a stream synchronisation that follows its
-// last copy (every Arnoldi step and every norm ends with one).
+// Pinned (coherent) host staging of the solvers' small transfers, in slots of
+// pin_slot doubles laid out like the device's: [norms | h1 h2 skip | sigma,
+// Givens state (3 slots) | y].  The reduction kernels write the norms, the
+// Hessenberg columns and the skip flag straight into it, and a one-block
+// kernel fetches the scales, Givens state and y from it (no copy engine on
+// the per-step round trip).  A region is rewritten by the host only after a
+// stream synchronisation that follows its last use by a kernel (every Arnoldi
+// step and every norm ends with one).
 size_t pin_slot(const Plan& pl) { return align_up(sizeof(double) * pl.g.B * MAXV) / sizeof(double); }
 
 double* pinned(Plan& pl) {
@@ -420,7 +424,7 @@ double* pinned(Plan& pl) {
     if (pl.pin) hipHostFree(pl.pin);
     pl.pin = nullptr;
     pl.pin_n = 0;
-    if (hipHostMalloc((void**)&pl.pin, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&pl.pin, sizeof(double) * n, hipHostMallocCoherent) != hipSuccess) {
       pl.pin = nullptr;
       return nullptr;
     }
@@ -431,9 +435,8 @@ double* pinned(Plan& pl) {
 
 // chunks: partial sums per right-hand side in sm.partial (<= 0: dot_chunks)
 void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s, int chunks = 0) {
-  timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s, chunks);
-  double* tmp = pl.pin;   // norms region
-  hipMemcpyAsync(tmp, sm.nrm, sizeof(double) * pl.g.B * MAXV, hipMemcpyDeviceToHost, s);
+  double* tmp = pl.pin;   // norms region, written by the reduction kernel
+  timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s, chunks, tmp);
   hipStreamSynchronize(s);
   out.resize(pl.g.B);
   // |.| keeps a NaN visible (std::max(0, NaN) would hide it)
@@ -620,9 +623,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       }
     };
     // the step's scales and Givens state, one copy
-    auto send_scales = [&]() {
-      hipMemcpyAsync(sm.sigma, sig, sizeof(double) * (ps + (size_t)B * GIVS), hipMemcpyHostToDevice, s);
-    };
+    auto send_scales = [&]() { fetch_host(sig, sm.sigma, (int)(ps + (size_t)B * GIVS), s); };
     stage_givens(0);
     send_scales();
     int j = 0;
@@ -647,7 +648,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         // otherwise the vector is kept as it is.
         {
           Timed t(pl, PD_STAGE_OTHER, s);
-          reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl));
+          reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl), hbuf);
         }
         // A step that ends its cycle (every live residual estimate within
         // rtol, or the restart length or iteration limit reached) needs no
@@ -658,14 +659,13 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         {
           Timed t(pl, PD_STAGE_OTHER, s);
           const bool force = j + 1 == m || iters + 1 >= o->max_iter;
-          arnoldi_skip(pl, sm.h1, sm.giv, GIVS, j, force, sm.skip, s);
+          arnoldi_skip(pl, sm.h1, sm.giv, GIVS, j, force, sm.skip, s, skiph);
         }
         const double upd_bytes = (double)g.NA * 8.0 * (j + 3);
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip, V0x);
-        timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s);
-        hipMemcpyAsync(hbuf, sm.h1, sizeof(double) * 2 * ps + sizeof(int), hipMemcpyDeviceToHost, s);
-        hipStreamSynchronize(s);
+        timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s, 0, h2buf);
+        hipStreamSynchronize(s);   // h1, h2 and the flag are in pinned memory
         skipped = *skiph != 0;
         second = false;
         if (skipped) {
@@ -756,7 +756,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       }
     }
     if (kmax > 0) {
-      hipMemcpyAsync(sm.y, yv, sizeof(double) * B * MAXV, hipMemcpyHostToDevice, s);
+      fetch_host(yv, sm.y, B * MAXV, s);
       Timed t(pl, PD_STAGE_OTHER, s, (double)g.NA * (16.0 + kmax * (double)zb), 2.0 * g.NA * kmax);
       x_update(pl, Z, zf32, zs, kmax, sm.y, u, !u_valid, s);
       u_valid = true;

@@ -165,9 +165,13 @@ void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const d
                double* partial, hipStream_t s);
 // h[b][i] = t s, coef[b][i] = t s^2 with t the reduced dot and s = sigma[b][i]
 // for i < nscaled (else 1): dots against unnormalised Krylov vectors.
-// chunks: partial sums per right-hand side (<= 0: dot_chunks).
+// chunks: partial sums per right-hand side (<= 0: dot_chunks).  hhost
+// (pinned host memory, same layout as h) also receives h when given.
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
-                     int nscaled, double* h, double* coef, hipStream_t s, int chunks = 0);
+                     int nscaled, double* h, double* coef, hipStream_t s, int chunks = 0,
+                     double* hhost = nullptr);
+// dst[0..n) = src[0..n) with src in pinned host memory (one small kernel).
+void fetch_host(const double* src, double* dst, int n, hipStream_t s);
 // w -= sum_i coef_i V_i (i < nv; V_0 at V0 instead when V0 is given), with
 // the partial dots of the result when want_dots; a no-op when skip is given
 // and *skip is set on the device.
@@ -178,7 +182,7 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 // (*flag = 1): h = first-pass coefficients plus w . w in slot j+1, giv = per
 // right-hand side [threshold, g_j, c_0..c_{j-1}, s_0..s_{j-1}] with stride gs.
 void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, int j, bool force,
-                  int* flag, hipStream_t s);
+                  int* flag, hipStream_t s, int* flag_host = nullptr);
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
               const double* y, double* x, bool overwrite, hipStream_t s);
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);

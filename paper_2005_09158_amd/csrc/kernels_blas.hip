@@ -351,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int
 __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partial, int nv, int chunks,
                                                const double* __restrict__ sigma, int nscaled,
                                                double* __restrict__ h, double* __restrict__ coef,
-                                               int ldh) {
+                                               int ldh, double* __restrict__ hhost) {
   __shared__ double red[4];
   const int b = blockIdx.y, i = blockIdx.x;
   double v = 0;
@@ -361,7 +361,15 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partia
     double sg = (sigma && i < nscaled) ? sigma[b * ldh + i] : 1.0;
     h[b * ldh + i] = t * sg;
     if (coef) coef[b * ldh + i] = t * sg * sg;
+    if (hhost) hhost[b * ldh + i] = t * sg;   // pinned host copy, read after the stream sync
   }
+}
+
+// dst[i] = src[i] for i < n: the solver's per-step scalars, staged by the
+// host in pinned memory, fetched by one small kernel instead of a copy.
+__global__ __launch_bounds__(NT) void k_fetch(const double* __restrict__ src, double* __restrict__ dst,
+                                              int n) {
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
 }
 
 // w[b] -= sum_i coef[b][i] V_i[b]; optionally partial dots of the new w with
@@ -493,7 +501,8 @@ __global__ __launch_bounds__(NT) void k_xupd4(const Tz* __restrict__ Z, int64_t 
 // (restart length or iteration limit reached): the next basis vector is then
 // never used.  One thread: a few multiply-adds per right-hand side.
 __global__ void k_arnoldi_skip(const double* __restrict__ h, const double* __restrict__ giv, int gs,
-                               int j, int B, int force, int* __restrict__ flag) {
+                               int j, int B, int force, int* __restrict__ flag,
+                               int* __restrict__ flag_host) {
   if (threadIdx.x != 0) return;
   bool all_done = true, well = true;
   for (int b = 0; b < B; ++b) {
@@ -513,7 +522,9 @@ __global__ void k_arnoldi_skip(const double* __restrict__ h, const double* __res
     const double est = fabs(hn / hypot(cur, hn) * G[1]);
     if (!(est <= thr)) all_done = false;
   }
-  *flag = (well && (force || all_done)) ? 1 : 0;
+  const int f = (well && (force || all_done)) ? 1 : 0;
+  *flag = f;
+  if (flag_host) *flag_host = f;
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -615,9 +626,14 @@ void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const d
 }
 
 void reduce_partials(const Plan& pl, const double* partial, int nv, const double* sigma,
-                     int nscaled, double* h, double* coef, hipStream_t s, int chunks) {
+                     int nscaled, double* h, double* coef, hipStream_t s, int chunks,
+                     double* hhost) {
   if (chunks <= 0) chunks = dot_chunks(pl);
-  k_reduce<<<dim3(nv, pl.g.B), NT, 0, s>>>(partial, nv, chunks, sigma, nscaled, h, coef, MAXV);
+  k_reduce<<<dim3(nv, pl.g.B), NT, 0, s>>>(partial, nv, chunks, sigma, nscaled, h, coef, MAXV, hhost);
+}
+
+void fetch_host(const double* src, double* dst, int n, hipStream_t s) {
+  k_fetch<<<1, NT, 0, s>>>(src, dst, n);
 }
 
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
@@ -640,8 +656,8 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 }
 
 void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, int j, bool force,
-                  int* flag, hipStream_t s) {
-  k_arnoldi_skip<<<1, 64, 0, s>>>(h, giv, gs, j, pl.g.B, force ? 1 : 0, flag);
+                  int* flag, hipStream_t s, int* flag_host) {
+  k_arnoldi_skip<<<1, 64, 0, s>>>(h, giv, gs, j, pl.g.B, force ? 1 : 0, flag, flag_host);
 }
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
