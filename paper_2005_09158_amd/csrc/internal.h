@@ -2,6 +2,9 @@
 #pragma once
 
 #include <complex>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -11,6 +14,23 @@
 #include "../../include/paradiag.h"
 
 namespace pd {
+
+// Raises a kernel's dynamic-LDS limit to `bytes` on the current device.  The
+// runtime call is made once per (device, kernel) and size, not per launch: on
+// a drained queue its cost shows up as idle time before the kernel.
+inline void lds_limit(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> done;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = done[{dev, fn}];
+  if (bytes > cur) {
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    cur = bytes;
+  }
+}
+
 
 using cd = std::complex<double>;
 

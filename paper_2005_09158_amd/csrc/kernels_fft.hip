@@ -665,8 +665,7 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, int bstri
   if (sh.n1 > 0) {
 #define PD_FWD4T(W, N, H)                                                                  \
   if (sh.TX == W && sh.n1 == N && sh.nth == H) {                                           \
-    hipFuncSetAttribute((const void*)k_fft4_fwd<T, W, N, H>,                               \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
+    lds_limit((const void*)k_fft4_fwd<T, W, N, H>, sh.lds);                                \
     k_fft4_fwd<T, W, N, H><<<grid, H, sh.lds, s>>>(x, spec, pl.d_gam, bscale, bstride, tw, g.nt, \
                                                    (int)g.S, g.sx, g.sy, reverse,          \
                                                    sh.gam_lds, sh.tw_lds);                 \
@@ -684,8 +683,7 @@ void launch_fwd(const Plan& pl, const double* x, const double* bscale, int bstri
   }
 #define PD_FWD(W)                                                                          \
   case W:                                                                                  \
-    hipFuncSetAttribute((const void*)k_fft_fwd<T, W>,                                      \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
+    lds_limit((const void*)k_fft_fwd<T, W>, sh.lds);                                       \
     k_fft_fwd<T, W><<<grid, NT, sh.lds, s>>>(x, spec, pl.d_gam, bscale, bstride, tw, g.nt, logNt, \
                                              (int)g.S, g.sx, g.sy, reverse, sh.gam_lds);   \
     break;
@@ -708,8 +706,7 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
     const size_t lds4 = sh.lds_inv;
 #define PD_INV4T(W, N, H)                                                                  \
   if (sh.TX == W && sh.n1 == N && sh.nth == H) {                                           \
-    hipFuncSetAttribute((const void*)k_fft4_inv<T, W, N, Tout, H>,                         \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);            \
+    lds_limit((const void*)k_fft4_inv<T, W, N, Tout, H>, lds4);                            \
     k_fft4_inv<T, W, N, Tout, H><<<grid, H, lds4, s>>>(spec, z, pl.d_invgam, tw, g.nt,     \
                                                        (int)g.S, g.sx, g.sy, accumulate,   \
                                                        reverse, sh.tw_lds);                \
@@ -727,8 +724,7 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
   }
 #define PD_INV(W)                                                                          \
   case W:                                                                                  \
-    hipFuncSetAttribute((const void*)k_fft_inv<T, W, Tout>,                                \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);          \
+    lds_limit((const void*)k_fft_inv<T, W, Tout>, sh.lds);                                 \
     k_fft_inv<T, W, Tout><<<grid, NT, sh.lds, s>>>(spec, z, pl.d_invgam, tw, g.nt, logNt,  \
                                                    (int)g.S, g.sx, g.sy, accumulate,       \
                                                    reverse);                               \

@@ -986,7 +986,7 @@ void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, BK>(pl);
   auto kfn = sh.vec ? k_schur_sweep_wide<T, R, P, NB, BK, RB, true> : k_schur_sweep_wide<T, R, P, NB, BK, RB, false>;
-  hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+  lds_limit((const void*)kfn, sh.lds);
   kfn<<<dim3(g.F, g.B), NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, (const T*)op.tup, (const T*)op.lu,
                                          op.lo, op.di, op.up, g.F, g.sx, g.sy, sh.ldy);
 }
@@ -1011,7 +1011,7 @@ void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   constexpr int MINB = (R == 4) ? 2 : 1;
   auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B>
                     : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B>;
-  hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  lds_limit((const void*)kfn, lds);
   kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
                                        g.F, g.sx, g.sy, sh.ldy);
 }

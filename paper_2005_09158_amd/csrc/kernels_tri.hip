@@ -115,8 +115,7 @@ void launch_lines(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
   const bool vec = (g.sx % 4) == 0;
 #define PD_LINE_K(RR, PP, TKV)                                                                    \
   {                                                                                               \
-    hipFuncSetAttribute((const void*)k_line_solve<T, RR, PP, TKV>,                                \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);                 \
+    lds_limit((const void*)k_line_solve<T, RR, PP, TKV>, sh.lds);                                 \
     k_line_solve<T, RR, PP, TKV><<<grid, NT, sh.lds, s>>>(spec, pl.d_lam, op.tk, op.lo, op.di,    \
                                                           op.up, g.F, g.sx, g.sy, sh.TK, sh.ldy); \
     return;                                                                                       \
