@@ -2,6 +2,7 @@
 // binding, and the drivers of the three solve modes.  See include/paradiag.h.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -414,12 +415,12 @@ namespace {
 // Hessenberg columns and the skip flag straight into it, and a one-block
 // kernel fetches the scales, Givens state and y from it (no copy engine on
 // the per-step round trip).  A region is rewritten by the host only after a
-// stream synchronisation that follows its last use by a kernel (every Arnoldi
-// step and every norm ends with one).
+// wait (wait_host) that follows its last use by a kernel (every Arnoldi step
+// and every norm ends with one).
 size_t pin_slot(const Plan& pl) { return align_up(sizeof(double) * pl.g.B * MAXV) / sizeof(double); }
 
 double* pinned(Plan& pl) {
-  const size_t n = 9 * pin_slot(pl);
+  const size_t n = 9 * pin_slot(pl) + 8;   // + the completion word (wait_host)
   if (pl.pin_n < n) {
     if (pl.pin) hipHostFree(pl.pin);
     pl.pin = nullptr;
@@ -429,15 +430,34 @@ double* pinned(Plan& pl) {
       return nullptr;
     }
     pl.pin_n = n;
+    std::memset(pl.pin, 0, sizeof(double) * n);   // the completion word starts below any wait's value
   }
   return pl.pin;
+}
+
+// Waits for the work queued on s so far by polling a completion word in the
+// pinned buffer (written by k_signal behind that work), which wakes the host
+// sooner than a stream synchronisation.  After about a second of polling it
+// falls back to the synchronisation (which also surfaces a failed launch).
+void wait_host(Plan& pl, hipStream_t s) {
+  int* word = reinterpret_cast<int*>(pl.pin + 9 * pin_slot(pl));
+  const int v = pl.seq = pl.seq % 0x3fffffff + 1;   // never 0 (the buffer starts zeroed)
+  signal_host(word, v, s);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (long it = 0;; ++it) {
+    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == v) return;
+    if ((it & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+      hipStreamSynchronize(s);
+      return;
+    }
+  }
 }
 
 // chunks: partial sums per right-hand side in sm.partial (<= 0: dot_chunks)
 void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s, int chunks = 0) {
   double* tmp = pl.pin;   // norms region, written by the reduction kernel
   timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s, chunks, tmp);
-  hipStreamSynchronize(s);
+  wait_host(pl, s);
   out.resize(pl.g.B);
   // |.| keeps a NaN visible (std::max(0, NaN) would hide it)
   for (int b = 0; b < pl.g.B; ++b) out[b] = std::sqrt(std::fabs(tmp[(size_t)b * MAXV]));
@@ -665,7 +685,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip, V0x);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s, 0, h2buf);
-        hipStreamSynchronize(s);   // h1, h2 and the flag are in pinned memory
+        wait_host(pl, s);   // h1, h2 and the flag are in pinned memory
         skipped = *skiph != 0;
         second = false;
         if (skipped) {

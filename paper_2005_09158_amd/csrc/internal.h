@@ -139,6 +139,7 @@ struct Plan {
   // pinned host staging of the solvers' small transfers (Krylov scalars, norms)
   double* pin = nullptr;
   size_t pin_n = 0;
+  int seq = 0;   // last value of the host-visible completion word (see wait_host)
 };
 
 size_t spec_elem_bytes(Prec p);          // 8 (double) or 4 (float)
@@ -192,6 +193,9 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
                      double* hhost = nullptr);
 // dst[0..n) = src[0..n) with src in pinned host memory (one small kernel).
 void fetch_host(const double* src, double* dst, int n, hipStream_t s);
+// *word = v (word in pinned host memory) once the work queued before it on s
+// has finished: the host polls it instead of synchronising the stream.
+void signal_host(int* word, int v, hipStream_t s);
 // w -= sum_i coef_i V_i (i < nv; V_0 at V0 instead when V0 is given), with
 // the partial dots of the result when want_dots; a no-op when skip is given
 // and *skip is set on the device.

@@ -365,6 +365,13 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partia
   }
 }
 
+// The completion word of a solver round trip: written once every kernel
+// queued before this one has finished (their stores to the coherent pinned
+// buffer are then visible to the host, which polls the word).
+__global__ void k_signal(int* __restrict__ word, int v) {
+  if (threadIdx.x == 0) *word = v;
+}
+
 // dst[i] = src[i] for i < n: the solver's per-step scalars, staged by the
 // host in pinned memory, fetched by one small kernel instead of a copy.
 __global__ __launch_bounds__(NT) void k_fetch(const double* __restrict__ src, double* __restrict__ dst,
@@ -635,6 +642,8 @@ void reduce_partials(const Plan& pl, const double* partial, int nv, const double
 void fetch_host(const double* src, double* dst, int n, hipStream_t s) {
   k_fetch<<<1, NT, 0, s>>>(src, dst, n);
 }
+
+void signal_host(int* word, int v, hipStream_t s) { k_signal<<<1, 64, 0, s>>>(word, v); }
 
 void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* coef,
                 double* w, double* partial, int want_dots, hipStream_t s, const int* skip,
