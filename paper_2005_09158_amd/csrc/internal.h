@@ -22,11 +22,11 @@ inline void lds_limit(const void* fn, size_t bytes) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, size_t> done;
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lock(mu);
   size_t& cur = done[{dev, fn}];
   if (bytes > cur) {
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     cur = bytes;
   }
 }
