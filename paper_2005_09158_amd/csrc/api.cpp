@@ -430,7 +430,7 @@ double* pinned(Plan& pl) {
       return nullptr;
     }
     pl.pin_n = n;
-    std::memset(pl.pin, 0, sizeof(double) * n);   // the completion word starts below any wait's value
+    std::memset(pl.pin, 0, sizeof(double) * n);
   }
   return pl.pin;
 }
@@ -441,7 +441,8 @@ double* pinned(Plan& pl) {
 // falls back to the synchronisation (which also surfaces a failed launch).
 void wait_host(Plan& pl, hipStream_t s) {
   int* word = reinterpret_cast<int*>(pl.pin + 9 * pin_slot(pl));
-  const int v = pl.seq = pl.seq % 0x3fffffff + 1;   // never 0 (the buffer starts zeroed)
+  const int v = pl.seq = pl.seq % 0x3fffffff + 1;   // never 0
+  __atomic_store_n(word, 0, __ATOMIC_RELEASE);       // whatever an earlier solve left there
   signal_host(word, v, s);
   const auto t0 = std::chrono::steady_clock::now();
   for (long it = 0;; ++it) {
