@@ -494,11 +494,18 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   if (!pinned(pl)) { set_error("pinned host staging allocation failed"); return PD_ERR_HIP; }
   // FGMRES from a zero guess takes V_0 = b: the first cycle reads it in place
   const bool fused_start = o->mode == PD_MODE_FGMRES && !o->use_x0;
-  std::vector<double> bn;
-  timed_dot(pl, b, 0, 1, b, sm.partial, s);
-  norms_from(pl, sm, bn, s);
-  for (int i = 0; i < B; ++i)
-    if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
+  // ... and, when it cannot end before its first Arnoldi step, starts that
+  // step from the unnormalised b: ||b|| then comes from the step's own matvec
+  // (which reads b for its first dot anyway) instead of a pass of its own, and
+  // the step's scalars are rescaled once it is known
+  const bool defer_norm = fused_start && o->rtol < 1.0 && o->max_iter >= 1;
+  std::vector<double> bn(B, 1.0);   // placeholders while defer_norm
+  if (!defer_norm) {
+    timed_dot(pl, b, 0, 1, b, sm.partial, s);
+    norms_from(pl, sm, bn, s);
+    for (int i = 0; i < B; ++i)
+      if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
+  }
   std::vector<int> it_rhs(B, 0);
   std::vector<double> res(B, 0.0);
   int iters = 0;
@@ -610,6 +617,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       norms_from(pl, sm, nr, s, matvec_chunks(pl));
     }
     const bool restart_cycle = !(first && fused_start);
+    // this cycle's step 0 runs on the unnormalised b (scale 1 until known)
+    const bool defer = first && defer_norm;
     first = false;
     bool all = rel(nr);
     for (int i = 0; i < B; ++i)
@@ -659,7 +668,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
           const double n = (double)g.NA;
           Timed t(pl, PD_STAGE_MATVEC, s, n * ((zf32 ? 4.0 : 8.0) + 8.0 + 8.0 * (j + 1)),
                   n * ((pl.L == 3 ? 22.0 : 18.0) + 2.0 * (j + 1)));
-          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial, 1, V0x);
+          matvec(pl, pl.op[variant], Zj(j), zf32, nullptr, w, variant, s, V, vs, j + 1, sm.partial, 1, V0x,
+                 (defer && j == 0) ? 1 : 0);
         }
         // classical Gram-Schmidt, two passes; the first pass's dots (and w . w)
         // come from the matvec kernel, the second pass's from the first pass's
@@ -669,7 +679,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         // otherwise the vector is kept as it is.
         {
           Timed t(pl, PD_STAGE_OTHER, s);
-          reduce_partials(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h1, sm.c1, s, matvec_chunks(pl), hbuf);
+          reduce_partials(pl, sm.partial, j + ((defer && j == 0) ? 3 : 2), sm.sigma, j + 1, sm.h1, sm.c1, s,
+                          matvec_chunks(pl), hbuf);
         }
         // A step that ends its cycle (every live residual estimate within
         // rtol, or the restart length or iteration limit reached) needs no
@@ -680,7 +691,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         {
           Timed t(pl, PD_STAGE_OTHER, s);
           const bool force = j + 1 == m || iters + 1 >= o->max_iter;
-          arnoldi_skip(pl, sm.h1, sm.giv, GIVS, j, force, sm.skip, s, skiph);
+          arnoldi_skip(pl, sm.h1, sm.giv, GIVS, j, force, sm.skip, s, skiph, defer && j == 0, sm.c1,
+                       sm.sigma, o->rtol);
         }
         const double upd_bytes = (double)g.NA * 8.0 * (j + 3);
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
@@ -688,6 +700,35 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s, 0, h2buf);
         wait_host(pl, s);   // h1, h2 and the flag are in pinned memory
         skipped = *skiph != 0;
+        if (defer && j == 0) {
+          // beta = ||b|| from slot 2; V_0 = b and z_0, w carry the factor
+          // beta against the unit-norm basis: h1 (dots taken with scale 1)
+          // and w . w scale by 1/beta^2, the second pass's dots (taken with
+          // the device's scale 1/beta) by 1/beta
+          bool any = false;
+          for (int i = 0; i < B; ++i) {
+            double* h1 = hbuf + (size_t)i * MAXV;
+            double* h2 = h2buf + (size_t)i * MAXV;
+            const double beta = std::sqrt(h1[2]);
+            if (!std::isfinite(beta)) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
+            bn[i] = beta;
+            nr[i] = beta;
+            gv[(size_t)i * (m + 1)] = beta;
+            active[i] = live[i] = beta > 0.0;
+            any = any || beta > 0.0;
+            const double r1 = beta > 0.0 ? 1.0 / beta : 0.0;
+            sig[(size_t)i * MAXV] = r1;
+            h1[0] *= r1 * r1;
+            h1[1] *= r1 * r1;
+            h2[0] *= r1;
+            h2[1] *= r1 * r1;
+            res[i] = beta > 0.0 ? 1.0 : 0.0;
+          }
+          if (!any) {   // b = 0: u = 0, nothing iterated
+            if (info && info->history && info->history_cap > 0) info->history[0] = 0.0;
+            return finish(true);
+          }
+        }
         second = false;
         if (skipped) {
           untime_last(pl, PD_STAGE_UPDATE, upd_bytes, upd_flops);   // it did not run
@@ -751,7 +792,9 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         est_max = std::max(est_max, est);
         if (est <= o->rtol || hn == 0.0) live[i] = 0;
         else any_live = true;
-        sig[(size_t)i * MAXV + j + 1] = (hn > 0 && live[i]) ? 1.0 / hn : 0.0;
+        // (the stored V_1 of a deferred step 0 carries the factor beta too)
+        const double vscale = (defer && j == 0) ? sig[(size_t)i * MAXV] : 1.0;
+        sig[(size_t)i * MAXV + j + 1] = (hn > 0 && live[i]) ? vscale / hn : 0.0;
       }
       push_hist(est_max);
       // a skipped update ends the cycle whatever the host's estimate says (w
@@ -775,6 +818,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         double d = Hc[(size_t)q * (m + 1) + q];
         y[q] = d != 0.0 ? acc / d : 0.0;
       }
+      // Z_0 of a deferred step 0 is beta z_0
+      if (defer && k > 0 && bn[i] > 0.0) y[0] /= bn[i];
     }
     if (kmax > 0) {
       fetch_host(yv, sm.y, B * MAXV, s);

@@ -169,11 +169,12 @@ void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills 
 // vectors Vk + i vstride (i < nv; vector 0 at V0 instead when V0 is given),
 // and with sq the partial sums of y . y (slot nv), one per workgroup
 // (matvec_chunks per right-hand side, layout as multi_dot's partial sums).
-// y may be null with sq: only the norm is formed.
+// y may be null with sq: only the norm is formed.  v0sq (nv >= 1): also
+// V_0 . V_0, in the slot after y . y (or after the dots without sq).
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk = nullptr,
             int64_t vstride = 0, int nv = 0, double* partial = nullptr, int sq = 0,
-            const double* V0 = nullptr);
+            const double* V0 = nullptr, int v0sq = 0);
 int matvec_chunks(const Plan& pl);
 void build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, double* b,
                hipStream_t s);
@@ -205,8 +206,12 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 // Device-side test whether Arnoldi step j ends its cycle without the update
 // (*flag = 1): h = first-pass coefficients plus w . w in slot j+1, giv = per
 // right-hand side [threshold, g_j, c_0..c_{j-1}, s_0..s_{j-1}] with stride gs.
+// first: step 0 of a cycle started from the unnormalised V_0 = b, whose h
+// carries b . b in slot 2; the kernel then also sets sigma[b][0] = 1/||b|| and
+// scales c1[b][0] by its square (see k_arnoldi_skip).
 void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, int j, bool force,
-                  int* flag, hipStream_t s, int* flag_host = nullptr);
+                  int* flag, hipStream_t s, int* flag_host = nullptr, bool first = false,
+                  double* c1 = nullptr, double* sigma = nullptr, double rtol = 0.0);
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
               const double* y, double* x, bool overwrite, hipStream_t s);
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);

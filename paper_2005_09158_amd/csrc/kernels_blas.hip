@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
                                                double c21, double c22, Stencil st, int chunk, int dir,
                                                const double* __restrict__ Vk, int64_t vstride, int nv,
                                                int sq, double* __restrict__ partial,
-                                               const double* __restrict__ V0) {
+                                               const double* __restrict__ V0, int v0sq) {
   constexpr int NR = NV > 0 ? NV : (NV < 0 ? MAXV : 1);
   __shared__ double red[4];
   const int S = nx * ny;
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
 #pragma unroll
   for (int i = 0; i < NR; ++i) acc[i] = 0.0;
   double asq = 0.0;   // y . y when sq
+  double abb = 0.0;   // V_0 . V_0 when v0sq
   if (s < S) {
   const int x = s % nx, y = s / nx;
   const int64_t boff = (int64_t)bp.z * Nt * S;
@@ -182,6 +183,9 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
           ldv<double, V>(((q == 0 && V0 != nullptr) ? V0 + boff : Vb + q * vstride) + off, vq);
 #pragma unroll
           for (int v = 0; v < V; ++v) acc[q] += vq[v] * r[v];
+          if (q == 0 && v0sq)
+#pragma unroll
+            for (int v = 0; v < V; ++v) abb += vq[v] * vq[v];
         }
     }
   };
@@ -223,6 +227,10 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
     if (sq) {
       const double t = block_sum(asq, red);
       if (threadIdx.x == 0) out[ndots] = t;
+    }
+    if (v0sq) {
+      const double t = block_sum(abb, red);
+      if (threadIdx.x == 0) out[ndots + (sq ? 1 : 0)] = t;
     }
   }
 }
@@ -509,24 +517,39 @@ __global__ __launch_bounds__(NT) void k_xupd4(const Tz* __restrict__ Z, int64_t 
 // never used.  One thread: a few multiply-adds per right-hand side.
 __global__ void k_arnoldi_skip(const double* __restrict__ h, const double* __restrict__ giv, int gs,
                                int j, int B, int force, int* __restrict__ flag,
-                               int* __restrict__ flag_host) {
+                               int* __restrict__ flag_host, int first, double* __restrict__ c1,
+                               double* __restrict__ sigma, double rtol) {
   if (threadIdx.x != 0) return;
   bool all_done = true, well = true;
   for (int b = 0; b < B; ++b) {
     const double* G = giv + (int64_t)b * gs;
-    const double thr = G[0];
-    if (thr < 0.0) continue;
     const double* hc = h + (int64_t)b * MAXV;
-    const double w2 = hc[j + 1];
-    double nn = w2, cur = hc[0];
-    for (int q = 0; q <= j; ++q) nn -= hc[q] * hc[q];
+    double thr = G[0], g = G[1], sc = 1.0;
+    if (first) {
+      // step 0 of a cycle started from the unnormalised V_0 = b: h[2] = b . b
+      // gives beta = ||b||, the scale of V_0 (for this step's update and the
+      // later reductions), the threshold rtol beta and g_0 = beta; the step's
+      // dots and w . w carry a factor beta^2
+      const double beta = sqrt(hc[2]);
+      const double s0 = beta > 0.0 ? 1.0 / beta : 0.0;
+      sigma[(int64_t)b * MAXV] = s0;
+      c1[(int64_t)b * MAXV] *= s0 * s0;
+      if (!(beta > 0.0)) continue;   // b = 0: not live (NaN: the host stops)
+      sc = s0 * s0;
+      thr = rtol * beta;
+      g = beta;
+    }
+    if (thr < 0.0) continue;
+    const double w2 = hc[j + 1] * sc;
+    double nn = w2, cur = hc[0] * sc;
+    for (int q = 0; q <= j; ++q) nn -= (hc[q] * sc) * (hc[q] * sc);
     for (int q = 0; q < j; ++q) {   // the previous rotations applied to the new column
-      const double c = G[2 + q], sn = G[2 + j + q], nx = hc[q + 1];
+      const double c = G[2 + q], sn = G[2 + j + q], nx = hc[q + 1] * sc;
       cur = -sn * cur + c * nx;
     }
     if (!(nn > 1e-12 * w2)) { well = false; continue; }
     const double hn = sqrt(nn);
-    const double est = fabs(hn / hypot(cur, hn) * G[1]);
+    const double est = fabs(hn / hypot(cur, hn) * g);
     if (!(est <= thr)) all_done = false;
   }
   const int f = (well && (force || all_done)) ? 1 : 0;
@@ -566,7 +589,7 @@ int matvec_chunks(const Plan& pl) {
 
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
             double* y, int transpose, hipStream_t s, const double* Vk, int64_t vstride, int nv,
-            double* partial, int sq, const double* V0) {
+            double* partial, int sq, const double* V0, int v0sq) {
   int V, chunk;
   const dim3 grid = matvec_grid(pl, V, chunk);
   Stencil st = stencil_of(op);
@@ -575,7 +598,7 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
 #define PD_MV(TIN, VV, K)                                                                         \
   k_matvec<TIN, VV, K><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0], \
                                            pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \
-                                           chunk, dir, Vk, vstride, nv, sq, partial, V0)
+                                           chunk, dir, Vk, vstride, nv, sq, partial, V0, v0sq)
 #define PD_MV_NV(TIN, VV)                                                                         \
   switch (nv) {                                                                                   \
     case 0: PD_MV(TIN, VV, 0); break;                                                             \
@@ -665,8 +688,10 @@ void update_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const 
 }
 
 void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, int j, bool force,
-                  int* flag, hipStream_t s, int* flag_host) {
-  k_arnoldi_skip<<<1, 64, 0, s>>>(h, giv, gs, j, pl.g.B, force ? 1 : 0, flag, flag_host);
+                  int* flag, hipStream_t s, int* flag_host, bool first, double* c1, double* sigma,
+                  double rtol) {
+  k_arnoldi_skip<<<1, 64, 0, s>>>(h, giv, gs, j, pl.g.B, force ? 1 : 0, flag, flag_host,
+                                  first ? 1 : 0, c1, sigma, rtol);
 }
 
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,

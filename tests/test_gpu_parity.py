@@ -255,6 +255,29 @@ def test_batch_matches_single_solves():
         assert r3.iters_per_rhs[i] == r1.iters
 
 
+def test_batch_with_zero_rhs():
+    # ||b|| of a zero-guess solve comes out of its first Arnoldi step: a zero
+    # right-hand side in a batch must stay inactive (zero solution, no
+    # iterations) while the others converge as when solved alone
+    announce("batch with a zero right-hand side")
+    params = CASES["2d-tr-schur"]
+    torch, pd3, prob = make(params, "fp64", batch=3)
+    b = np.random.default_rng(12).standard_normal((3, prob.nt, prob.nspace))
+    b[1] = 0.0
+    u3, r3 = pd3.solve(to_gpu(torch, b, pd3.shape), rtol=1e-12, max_iter=60)
+    assert r3.converged
+    assert float(u3[1].abs().max()) == 0.0
+    assert r3.iters_per_rhs[1] == 0 and r3.resid_per_rhs[1] == 0.0
+    assert r3.history[0] == 1.0
+    _, pd1, _ = make(params, "fp64", batch=1)
+    for i in (0, 2):
+        u1, r1 = pd1.solve(to_gpu(torch, b[i], pd1.shape), rtol=1e-12, max_iter=60)
+        assert rel_err(u3[i].cpu().numpy(), u1[0].cpu().numpy()) < 1e-13
+        assert r3.iters_per_rhs[i] == r1.iters
+        ref = o_solve.sequential(prob, b[i])
+        assert rel_err(u3[i].cpu().numpy().reshape(prob.nt, -1), ref) < 1e-9
+
+
 def test_error_paths():
     announce("error paths")
     torch, pd, prob = make(CASES["2d-tr-schur"], "fp64")
@@ -271,6 +294,7 @@ def test_error_paths():
     # zero right-hand side: zero solution, converged without iterations
     u, res = pd.solve(torch.zeros_like(b), rtol=1e-8)
     assert res.converged and float(u.abs().max()) == 0.0
+    assert res.iters == 0 and res.history[:1] == [0.0] and res.rel_resid == 0.0
     # workspace too small for a longer restart than bound
     with pytest.raises(ParaDiagError) as e:
         pd.solve(b, rtol=1e-8, restart=30)
