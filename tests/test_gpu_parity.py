@@ -278,6 +278,31 @@ def test_batch_with_zero_rhs():
         assert rel_err(u3[i].cpu().numpy().reshape(prob.nt, -1), ref) < 1e-9
 
 
+def test_zero_guess_start_variants():
+    # the start from a zero guess has three forms: ||b|| deferred into the
+    # first Arnoldi step (the usual one), a separate norm pass (rtol >= 1,
+    # where the solve ends before any step) and an explicit zero x0 (the
+    # restart path): they must agree
+    announce("zero-guess start variants")
+    params = CASES["2d-tr-schur"]
+    torch, pd3, prob = make(params, "fp64", batch=3)
+    b = np.random.default_rng(13).standard_normal((3, prob.nt, prob.nspace))
+    b[2] = 0.0
+    bg = to_gpu(torch, b, pd3.shape)
+    u, res = pd3.solve(bg, rtol=1.5)
+    assert res.converged and res.iters == 0 and float(u.abs().max()) == 0.0
+    assert res.history[:1] == [1.0]
+    ua, ra = pd3.solve(bg, rtol=1e-12, max_iter=60, restart=1)
+    ub, rb = pd3.solve(bg, rtol=1e-12, max_iter=60, restart=1, x0=torch.zeros_like(bg))
+    assert ra.converged and rb.converged
+    assert ra.iters_per_rhs[2] == 0 and float(ua[2].abs().max()) == 0.0
+    for i in (0, 1):
+        assert rel_err(ua[i].cpu().numpy(), ub[i].cpu().numpy()) < 1e-10
+        assert ra.iters_per_rhs[i] == rb.iters_per_rhs[i]
+        ref = o_solve.sequential(prob, b[i])
+        assert rel_err(ua[i].cpu().numpy().reshape(prob.nt, -1), ref) < 1e-9
+
+
 def test_error_paths():
     announce("error paths")
     torch, pd, prob = make(CASES["2d-tr-schur"], "fp64")
