@@ -514,7 +514,12 @@ __global__ __launch_bounds__(NT) void k_xupd4(const Tz* __restrict__ Z, int64_t 
 // live right-hand side (w . w - sum h^2 above 1e-12 w . w) and either every
 // estimate is within its threshold or the host forces the end of the cycle
 // (restart length or iteration limit reached): the next basis vector is then
-// never used.  One thread: a few multiply-adds per right-hand side.
+// never used.  With `first` (step 0 of a cycle run on the unnormalised
+// V_0 = b, whose h[b][2] holds b . b) the kernel also derives beta = ||b||:
+// it stores the V_0 scale 1/beta in sigma, scales the first-pass coefficient
+// in c1 by 1/beta^2 before the update reads it, and tests against rtol beta
+// with g_0 = beta.  A zero b is then not live.  One thread: a few
+// multiply-adds per right-hand side.
 __global__ void k_arnoldi_skip(const double* __restrict__ h, const double* __restrict__ giv, int gs,
                                int j, int B, int force, int* __restrict__ flag,
                                int* __restrict__ flag_host, int first, double* __restrict__ c1,
