@@ -278,6 +278,29 @@ def test_batch_with_zero_rhs():
         assert rel_err(u3[i].cpu().numpy().reshape(prob.nt, -1), ref) < 1e-9
 
 
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_mixed_batch_with_zero_rhs(adjoint):
+    # the deferred right-hand-side norm in mixed precision, for A and A^T:
+    # right-hand sides of very different scales and a zero one in one batch
+    announce(f"mixed batch with a zero right-hand side, adjoint={adjoint}")
+    torch, pd3, prob = make(CASES["2d-tr-schur"], "fp32_bf16gemm", batch=3)
+    b = np.random.default_rng(14).standard_normal((3, prob.nt, prob.nspace))
+    b[0] *= 1e4
+    b[1] = 0.0
+    b[2] *= 1e-4
+    bg = to_gpu(torch, b, pd3.shape)
+    solve = pd3.adjoint_solve if adjoint else pd3.solve
+    u, res = solve(bg, rtol=1e-10, max_iter=60)
+    assert res.converged, res
+    assert float(u[1].abs().max()) == 0.0 and res.iters_per_rhs[1] == 0
+    apply = ops.apply_AT if adjoint else ops.apply_A
+    for i in (0, 2):
+        un = u[i].cpu().numpy().reshape(prob.nt, -1)
+        true_res = np.linalg.norm(b[i] - apply(prob, un)) / np.linalg.norm(b[i])
+        print(f"  rhs {i}: iters {res.iters_per_rhs[i]} true residual {true_res:.2e}")
+        assert true_res <= 1.01e-10
+
+
 def test_zero_guess_start_variants():
     # the start from a zero guess has three forms: ||b|| deferred into the
     # first Arnoldi step (the usual one), a separate norm pass (rtol >= 1,
