@@ -28,8 +28,11 @@
  *   ny = 1 for one space dimension.  Pointers must be 8-byte aligned.
  * Ownership.  The caller owns every vector and the workspace (device memory
  *   obtained from any allocator, e.g. PyTorch's).  A plan owns host tables
- *   only; its device tables live inside the bound workspace.  The library
- *   allocates no device memory.  A plan is not thread-safe.
+ *   and, from its first solve on, a small pinned host buffer for the solvers'
+ *   per-step scalars (freed by paradiag_destroy); its device tables live
+ *   inside the bound workspace.  The library allocates no device memory.  A
+ *   plan is not thread-safe, and two solves with one plan must not overlap
+ *   in time, even on different streams (they share that buffer).
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Every
  *   call is ordered on that stream.  matvec, apply_precond and build_rhs only
  *   enqueue work; solve and adjoint_solve synchronise the stream once per
