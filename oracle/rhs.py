@@ -22,8 +22,11 @@ U_{-1} = U_1 - 2 dt u_1 (central difference of the initial velocity u_1):
 Source f is sampled at the Nt+1 time levels t_0..t_Nt, shape [nt+1][nspace].
 
 Pins: manufactured solutions converge at the order of the scheme
-(tests/test_oracle_discretisation.py), which fails for a wrong weight or sign
-in any of these rows; the transpose passes the dot-product identity.
+(tests/test_oracle_solve.py); with K = 0 every scheme reduces to a quadrature
+of the source with a closed-form discrete solution, which separates f_n from
+f_{n-1} in the backward Euler row and fixes the two leap-frog start rows
+(tests/test_oracle_rhs.py); the transpose passes the dot-product identity
+(tests/test_oracle_adjoint.py).
 """
 
 from __future__ import annotations

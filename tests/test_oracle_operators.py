@@ -127,3 +127,21 @@ def test_advection_factor_spectrum():
     ev = 2 * nu / h ** 2 - 2 * np.sqrt(b * c) * np.cos(k * np.pi / (n + 1))
     got = np.sort(np.linalg.eigvals(K).real)
     np.testing.assert_allclose(got, np.sort(ev), rtol=1e-8)
+
+
+@pytest.mark.parametrize("n", [5, 8, 16])
+def test_periodic_factor_is_the_circulant_of_eq2_2b(n):
+    # Periodic boundaries (eq2.2b with its corner entries): K is circulant, so
+    # the Fourier modes w_j = e^{2 pi i k j / n} are eigenvectors with the
+    # closed-form eigenvalues (4 nu / h^2) sin^2(pi k / n) + i (a / h) sin(2 pi k / n).
+    nu, a = 0.03, 1.7
+    K = ops.k1d(n, nu, a, periodic=True).toarray()
+    h = ops.mesh_width(n, periodic=True)
+    assert h == 1.0 / n
+    k = np.arange(n)
+    lam = 4 * nu / h ** 2 * np.sin(np.pi * k / n) ** 2 + 1j * (a / h) * np.sin(2 * np.pi * k / n)
+    W = np.exp(2j * np.pi * np.outer(np.arange(n), k) / n)
+    np.testing.assert_allclose(K @ W, W * lam[None, :], atol=1e-12 * np.abs(lam).max())
+    # every row holds the same stencil, wrapped at the ends
+    for i in range(n):
+        np.testing.assert_allclose(np.roll(K[i], -i), np.roll(K[0], 0), atol=0)
