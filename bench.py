@@ -8,14 +8,25 @@ The mixed-precision preconditioner (float32 FFT and line solves, bf16 MFMA
 x-transform) is timed next to the plain float64 one on the same problem;
 `value` is the mixed-precision rate.
 
-The JSON line also carries the roofline of the dominant kernel (algorithmic
-bytes or flops per launch over the average launch time, both measured by the
-library with HIP events on the solve's stream during the timed steps) and a
-CPU baseline: the float64 oracle's sequential time stepper on the same
-problem, timed on the host.  One extra solve before the timed region, with
-every stage timed, gives the per-stage breakdown and picks the dominant
-stage; inside the timed region only that stage records events, since every
-event pair costs a few microseconds of stream time.
+The default workload is 2D advection-diffusion on 512 x 512 interior points,
+Nt = 1024 trapezoidal steps, with a batch of 8 source terms solved in one
+launch (2.15e9 space-time unknowns).
+
+The JSON line also carries
+* the roofline of the dominant kernel (algorithmic bytes or flops per launch
+  over the average launch time, both measured by the library with HIP events
+  on the solve's stream during the timed steps);
+* the error of right-hand side 0 against the float64 oracle's sequential time
+  stepper over the whole horizon, for both precisions (computed after the
+  timed region);
+* CPU baselines: the oracle's sequential stepper on that right-hand side
+  (one core; it also yields the error reference), and a sample of the
+  oracle's own ParaDiag-II preconditioner with Step-(b) spread over the host
+  cores, scaled to a whole solve.
+One extra solve before the timed region, with every stage timed, gives the
+per-stage breakdown and picks the dominant stage; inside the timed region only
+that stage records events, since every event pair costs a few microseconds of
+stream time.
 """
 
 from __future__ import annotations
@@ -52,11 +63,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--mixed", default="fp32_bf16gemm", choices=["fp32", "fp32_bf16gemm", "fp32_bf16x1"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--mixed", default=None, choices=["fp32", "fp32_bf16gemm", "fp32_bf16x1"],
+                    help="reduced-precision preconditioner (default: the workload's own; float32 "
+                         "for the wave equation, split-bf16 x-transform otherwise)")
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the oracle's sequential solve (no error_vs_oracle, no cpu_baseline)")
     ap.add_argument("--traffic", default=None,
                     help="profile summary holding a 'traffic: {...}' line with the measured HBM "
                          "bytes per launch of the dominant kernel (default: profiles/<kernel>_<workload>_traffic.md)")
@@ -143,9 +158,12 @@ def run_precision(cfg, prec, args, torch):
                rel_resid=max(r.rel_resid for r in results),
                converged=all(r.converged for r in results), stages=stages, dominant=dominant,
                dominant_timed=timed[dominant])
-    u_keep = u
-    del b
-    return out, pd, u_keep
+    # right-hand side 0 of the last timed solve, for the error against the
+    # oracle (outside the timed region)
+    u0 = u[0].cpu().numpy().reshape(cfg.nt, -1)
+    del b, u, pd
+    torch.cuda.empty_cache()
+    return out, u0
 
 
 KERNEL_SOURCES = {"k_schur_sweep": ("kernels_sweep.hip", "tri_device.h")}
@@ -221,31 +239,99 @@ def stage_rooflines(run):
     return out
 
 
-def cpu_baseline(cfg):
-    """The oracle's sequential float64 time stepper on one right-hand side (host, 1 thread)."""
+def oracle_reference(cfg):
+    """The oracle's right-hand side 0 and its solution by sequential float64
+    time stepping over the whole horizon (one sparse LU, then Nt triangular
+    solves, one thread), with the wall time of the stepping."""
     from threadpoolctl import threadpool_limits
     from oracle import Problem, rhs, solve
     from workloads import initial_state, initial_velocity, source_term
     p = Problem.from_kwargs(**cfg.problem_kwargs())
-    nt_sample = p.nt
-    # bound the host work: at most ~2e7 space-time unknowns (cfg3/cfg5 solve a prefix of
-    # the time steps; the stepper's cost is linear in the number of steps)
-    while nt_sample * p.nspace > 4e7 and nt_sample > 16:
-        nt_sample //= 2
     with threadpool_limits(1):
         U0 = initial_state(cfg)
         f = source_term(cfg, cfg.seed + 1) if cfg.with_source else None
         u1 = initial_velocity(cfg) if cfg.scheme == "lf" else None
         b = rhs.build_rhs(p, U0, u1, f)
+        del f
         t0 = time.perf_counter()
-        ps = Problem.from_kwargs(**{**cfg.problem_kwargs(), "nt": nt_sample,
-                                   "T": cfg.T * nt_sample / cfg.nt})
-        solve.sequential(ps, b[:nt_sample])
+        ref = solve.sequential(p, b)
         dt = time.perf_counter() - t0
-    return {"value": nt_sample * p.nspace / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential float64 time stepping (one sparse LU + {nt_sample} triangular "
-                      f"solves) of 1 right-hand side, {nt_sample} of {p.nt} steps, "
-                      f"{p.nspace} unknowns per step; {dt:.1f} s"}
+    return p, ref, dt
+
+
+def error_vs_oracle(u, ref):
+    """Relative error of one right-hand side's solution: max norm and 2-norm."""
+    d = u - ref
+    return {"max_rel": float(np.abs(d).max() / np.abs(ref).max()),
+            "l2_rel": float(np.linalg.norm(d) / np.linalg.norm(ref))}
+
+
+def _stepb_worker(args):
+    """One Step-(b) solve of the oracle at frequency n (a worker process)."""
+    kw, n = args
+    from threadpoolctl import threadpool_limits
+    from oracle import Problem, precond
+    p = Problem.from_kwargs(**kw)
+    s1 = np.random.default_rng(n).standard_normal(p.nspace) + 1j * np.random.default_rng(n + 1).standard_normal(p.nspace)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        precond.frequency_solve(p, n, s1)
+        return time.perf_counter() - t0
+
+
+def cpu_paradiag_sample(cfg, cores):
+    """Wall time of Step-(b) of the oracle's ParaDiag-II preconditioner on
+    `cores` frequencies at once, one sparse LU and solve per frequency and per
+    worker process: the paper's own parallelisation across time points on one
+    node.  Run before the GPU is touched (the workers are forked)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    kw = cfg.problem_kwargs()
+    freqs = [1 + (k * (cfg.nt - 1)) // cores for k in range(cores)]
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
+        per = list(ex.map(_stepb_worker, [(kw, n) for n in freqs]))
+    wall = time.perf_counter() - t0
+    return {"wall_s": wall, "freqs": len(freqs), "per_freq_s": float(np.mean(per))}
+
+
+def cpu_baselines(cfg, ref_dt, sample, iters):
+    """cpu_baseline (sequential oracle stepper) and the scaled CPU ParaDiag-II figure."""
+    U1 = cfg.nx * cfg.ny * cfg.nt   # unknowns of one right-hand side
+    base = {"value": U1 / ref_dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential float64 time stepping of right-hand side 0 of {cfg.batch} "
+                      f"(one sparse LU + {cfg.nt} triangular solves, the whole horizon, "
+                      f"{cfg.nx * cfg.ny} unknowns per step); {ref_dt:.1f} s"}
+    if sample is None:
+        return base, None
+    cores = sample["freqs"]
+    # one preconditioner application needs nt frequency solves; `cores` ran
+    # side by side in sample["wall_s"]
+    per_app = sample["wall_s"] * cfg.nt / cores
+    solve_s = per_app * iters
+    para = {"value": U1 / solve_s, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"Step-(b) of the oracle's ParaDiag-II preconditioner (complex sparse LU and "
+                      f"solve per frequency) on {cores} of {cfg.nt} frequencies, one per worker "
+                      f"process, {sample['wall_s']:.1f} s wall ({sample['per_freq_s']:.1f} s per "
+                      f"frequency); scaled to {cfg.nt} frequencies x {iters} preconditioner "
+                      f"applications (the float64 FGMRES count) for right-hand side 0. Steps (a), "
+                      f"(c), the matvec and Gram-Schmidt are left out, so this overstates the rate"}
+    return base, para
+
+
+def workload_name(cfg):
+    if cfg.dim == 1:
+        return (f"{cfg.name}: 1D advection-diffusion {cfg.nx} points, Nt {cfg.nt}, "
+                f"{cfg.scheme.upper()}, alpha {cfg.alpha}, batch {cfg.batch}")
+    pde = "2D wave equation" if cfg.scheme == "lf" else "2D advection-diffusion"
+    scheme = {"lf": "implicit leap-frog", "tr": "TR", "be": "BE"}[cfg.scheme]
+    return (f"{cfg.name}: {pde} {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, {scheme}, alpha {cfg.alpha}, "
+            f"batch {cfg.batch}")
+
+
+DTYPE = {"fp32_bf16gemm": "f64 krylov + f32 fft/line solves + split-bf16 mfma x-transform",
+         "fp32_bf16x1": "f64 krylov + f32 fft/line solves + bf16 mfma x-transform",
+         "fp32": "f64 krylov + f32 preconditioner"}
 
 
 def main():
@@ -257,25 +343,28 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    from workloads import CONFIGS
+    cfg = CONFIGS[args.workload]
+    mixed_prec = args.mixed or (cfg.prec if cfg.prec != "fp64" else "fp32_bf16gemm")
+    # the CPU ParaDiag-II sample forks worker processes: before the GPU is touched
+    sample = None
+    if not args.no_cpu_baseline:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        print(f"[bench] CPU ParaDiag-II sample on {cores} worker processes", file=sys.stderr, flush=True)
+        sample = cpu_paradiag_sample(cfg, cores)
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    from workloads import CONFIGS
-    cfg = CONFIGS[args.workload]
     torch.cuda.set_device(0)
     print(f"[bench] workload {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.nt} batch {cfg.batch} "
           f"scheme {cfg.scheme} alpha {cfg.alpha}", file=sys.stderr, flush=True)
-    mixed, pdm, um = run_precision(cfg, args.mixed, args, torch)
-    print(f"[bench] {args.mixed}: {mixed['ms_per_step']:.3f} ms/solve iters {mixed['iters']} "
+    mixed, um = run_precision(cfg, mixed_prec, args, torch)
+    print(f"[bench] {mixed_prec}: {mixed['ms_per_step']:.3f} ms/solve iters {mixed['iters']} "
           f"resid {mixed['rel_resid']:.2e}", file=sys.stderr, flush=True)
-    del pdm, um
-    torch.cuda.empty_cache()
-    fp64 = None
+    fp64, u64 = None, None
     if not args.skip_fp64:
-        fp64, pd64, u64 = run_precision(cfg, "fp64", args, torch)
-        del pd64, u64
-        torch.cuda.empty_cache()
+        fp64, u64 = run_precision(cfg, "fp64", args, torch)
         print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/solve iters {fp64['iters']} "
               f"resid {fp64['rel_resid']:.2e}", file=sys.stderr, flush=True)
     U = cfg.unknowns
@@ -291,13 +380,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32_bf16gemm": "f64 krylov + f32 fft/line solves + split-bf16 mfma x-transform",
-                  "fp32_bf16x1": "f64 krylov + f32 fft/line solves + bf16 mfma x-transform",
-                  "fp32": "f64 krylov + f32 preconditioner"}[args.mixed],
+        "dtype": DTYPE[mixed_prec],
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: 2D advection-diffusion {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, "
-                               f"{cfg.scheme.upper()}, alpha {cfg.alpha}, batch {cfg.batch}"
-                   if cfg.dim == 2 else f"{cfg.name}", "nx": cfg.nx, "ny": cfg.ny, "nt": cfg.nt,
+        "config": {"workload": workload_name(cfg), "nx": cfg.nx, "ny": cfg.ny, "nt": cfg.nt,
                    "batch": cfg.batch, "unknowns": U, "rtol": cfg.rtol, "restart": args.restart},
         "mixed": {k: v for k, v in mixed.items() if k not in ("stages", "dominant_timed")},
         "fp64": None if fp64 is None else {k: v for k, v in fp64.items()
@@ -312,9 +397,20 @@ def main():
         "roofline": roofline(mixed, cfg, args.traffic),
         "stage_roofline": stage_rooflines(mixed),
     }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_oracle:
+        print("[bench] float64 oracle: sequential time stepping of right-hand side 0", file=sys.stderr,
+              flush=True)
+        _, ref, ref_dt = oracle_reference(cfg)
+        line["error_vs_oracle"] = {
+            "rhs": 0, "oracle": "sequential float64 time stepping, whole horizon",
+            "mixed": error_vs_oracle(um, ref),
+            "fp64": None if u64 is None else error_vs_oracle(u64, ref)}
+        iters64 = max(fp64["iters"]) if fp64 else max(mixed["iters"])
+        base, para = cpu_baselines(cfg, ref_dt, sample, iters64)
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = base
+            if para:
+                line["cpu_baseline_paradiag_ii"] = para
     print(json.dumps(line), flush=True)
 
 

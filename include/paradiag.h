@@ -78,8 +78,10 @@ typedef enum {
                                  operands split into three bf16 parts (six products:
                                  float32-level accuracy at bf16 instruction rate) */
   PD_PREC_FP32_BF16X1 = 3     /* as FP32; x-transform as one bf16 product (fastest, least
-                                 accurate: the preconditioner error grows with the
-                                 non-normality of K_x) */
+                                 accurate).  Symmetric K_x only (sine basis): with a
+                                 non-normal K_x setup returns PD_ERR_UNSUPPORTED, since
+                                 the back-substitution over the Schur factor carries the
+                                 bf16 rounding into an error of order one */
 } paradiag_prec;
 
 typedef enum {

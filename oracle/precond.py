@@ -35,17 +35,27 @@ def assembled(p: Problem, r, alpha: float | None = None) -> np.ndarray:
     return z.reshape(p.nt, p.nspace)
 
 
+def frequency_solve(p: Problem, n: int, s1: np.ndarray, alpha: float | None = None,
+                    K=None) -> np.ndarray:
+    """Step-(b) at one frequency n: (lambda1_n I + lambda2_n K)^{-1} s1 (eq2.12).
+
+    K (the complex spatial matrix) may be passed in to skip its assembly."""
+    lam1, lam2 = time_symbols(p, alpha)
+    if K is None:
+        K = spatial_operator(p).astype(np.complex128)
+    I = sp.identity(p.nspace, dtype=np.complex128)
+    M = (lam1[n] * I + lam2[n] * K).tocsc()
+    return spla.splu(M).solve(np.asarray(s1, dtype=np.complex128))
+
+
 def spectrum_solve(p: Problem, S1: np.ndarray, alpha: float | None = None,
                    freqs=None) -> np.ndarray:
     """Step-(b) on the given frequencies: S2_n = (lambda1_n I + lambda2_n K)^{-1} S1_n."""
-    lam1, lam2 = time_symbols(p, alpha)
     K = spatial_operator(p).astype(np.complex128)
-    I = sp.identity(p.nspace, dtype=np.complex128)
     S2 = np.zeros_like(S1, dtype=np.complex128)
     idx = range(p.nt) if freqs is None else freqs
     for n in idx:
-        M = (lam1[n] * I + lam2[n] * K).tocsc()
-        S2[n] = spla.splu(M).solve(S1[n])
+        S2[n] = frequency_solve(p, n, S1[n], alpha, K)
     return S2
 
 

@@ -95,6 +95,13 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
   }
   if (p.dim == 1 && p.nx > 2048) { set_error("nx > 2048 unsupported in 1D"); return PD_ERR_UNSUPPORTED; }
   if (p.dim == 2 && (p.ny > 2048 || p.nx > 2048)) { set_error("nx, ny > 2048 unsupported"); return PD_ERR_UNSUPPORTED; }
+  if (p.dim == 2 && p.ax != 0.0 && p.prec == PD_PREC_FP32_BF16X1) {
+    // one bf16 rounding (2^-9) of the x-transform operands, carried through the
+    // back-substitution over the non-normal Schur factor, leaves the
+    // preconditioner error of order one: no stated accuracy can be met
+    set_error("single-bf16 x-transform needs a symmetric x factor (use PD_PREC_FP32_BF16GEMM)");
+    return PD_ERR_UNSUPPORTED;
+  }
   if (p.dim == 2 && p.ax != 0.0 && p.nx > 1024) {
     set_error("non-symmetric x factor with nx > 1024 unsupported (host Schur cost)"); return PD_ERR_UNSUPPORTED;
   }
@@ -437,31 +444,50 @@ double* pinned(Plan& pl) {
 
 // Waits for the work queued on s so far by polling a completion word in the
 // pinned buffer (written by k_signal behind that work), which wakes the host
-// sooner than a stream synchronisation.  After about a second of polling it
-// falls back to the synchronisation (which also surfaces a failed launch).
-void wait_host(Plan& pl, hipStream_t s) {
+// sooner than a stream synchronisation.  k_signal makes every earlier write
+// of the stream visible at system scope before it stores the word (release),
+// and the host reads the word with acquire ordering before it reads the
+// pinned results.  After about a second of polling it falls back to the
+// synchronisation.  Returns PD_OK, or PD_ERR_HIP (message set) when a launch
+// failed or the stream reports an error: the caller must then return at once,
+// without reading the pinned buffer.
+paradiag_status wait_host(Plan& pl, hipStream_t s) {
   int* word = reinterpret_cast<int*>(pl.pin + 9 * pin_slot(pl));
   const int v = pl.seq = pl.seq % 0x3fffffff + 1;   // never 0
   __atomic_store_n(word, 0, __ATOMIC_RELEASE);       // whatever an earlier solve left there
   signal_host(word, v, s);
+  auto failed = [](const char* what, hipError_t e) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PD_ERR_HIP;
+  };
+  // a launch that failed (this one or one before it) never signals
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return failed("kernel launch", e);
   const auto t0 = std::chrono::steady_clock::now();
   for (long it = 0;; ++it) {
-    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == v) return;
+    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == v) break;
     if ((it & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
-      hipStreamSynchronize(s);
-      return;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return failed("stream synchronisation", e);
+      break;
     }
   }
+  e = hipGetLastError();
+  if (e != hipSuccess) return failed("solver step", e);
+  return PD_OK;
 }
 
 // chunks: partial sums per right-hand side in sm.partial (<= 0: dot_chunks)
-void norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s, int chunks = 0) {
+paradiag_status norms_from(Plan& pl, Small& sm, std::vector<double>& out, hipStream_t s,
+                           int chunks = 0) {
   double* tmp = pl.pin;   // norms region, written by the reduction kernel
   timed_reduce(pl, sm.partial, 1, nullptr, 0, sm.nrm, nullptr, s, chunks, tmp);
-  wait_host(pl, s);
+  paradiag_status st = wait_host(pl, s);
+  if (st != PD_OK) return st;
   out.resize(pl.g.B);
   // |.| keeps a NaN visible (std::max(0, NaN) would hide it)
   for (int b = 0; b < pl.g.B; ++b) out[b] = std::sqrt(std::fabs(tmp[(size_t)b * MAXV]));
+  return PD_OK;
 }
 
 
@@ -502,7 +528,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
   std::vector<double> bn(B, 1.0);   // placeholders while defer_norm
   if (!defer_norm) {
     timed_dot(pl, b, 0, 1, b, sm.partial, s);
-    norms_from(pl, sm, bn, s);
+    if (paradiag_status st = norms_from(pl, sm, bn, s); st != PD_OK) return st;
     for (int i = 0; i < B; ++i)
       if (!std::isfinite(bn[i])) { set_error("right-hand side contains NaN or Inf"); return PD_ERR_NONFINITE; }
   }
@@ -552,7 +578,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     // norm only)
     std::vector<double> nr;
     apply_A(pl, variant, u, false, b, nullptr, s, sm.partial);
-    norms_from(pl, sm, nr, s, matvec_chunks(pl));
+    if (paradiag_status st = norms_from(pl, sm, nr, s, matvec_chunks(pl)); st != PD_OK) return st;
     rel(nr);
     push_hist(*std::max_element(res.begin(), res.end()));
     return finish(true);
@@ -564,7 +590,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
     std::vector<double> nr;
     while (true) {
       apply_A(pl, variant, u, false, b, r, s, sm.partial);
-      norms_from(pl, sm, nr, s, matvec_chunks(pl));
+      if (paradiag_status st = norms_from(pl, sm, nr, s, matvec_chunks(pl)); st != PD_OK) return st;
       bool all = rel(nr);
       for (int i = 0; i < B; ++i)
         if (!std::isfinite(res[i])) { set_error("non-finite residual"); return PD_ERR_NONFINITE; }
@@ -614,7 +640,7 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
       // another cycle follows
       if (!u_valid) { fill_zero(u, g.NA, s); u_valid = true; }
       apply_A(pl, variant, u, false, b, nullptr, s, sm.partial);
-      norms_from(pl, sm, nr, s, matvec_chunks(pl));
+      if (paradiag_status st = norms_from(pl, sm, nr, s, matvec_chunks(pl)); st != PD_OK) return st;
     }
     const bool restart_cycle = !(first && fused_start);
     // this cycle's step 0 runs on the unnormalised b (scale 1 until known)
@@ -698,7 +724,8 @@ static paradiag_status solve_impl(Plan& pl, int variant, const double* b, double
         const double upd_flops = (double)g.NA * (4.0 * (j + 1) + 2.0);
         timed_update(pl, V, vs, j + 1, sm.c1, w, sm.partial, 1, s, sm.skip, V0x);
         timed_reduce(pl, sm.partial, j + 2, sm.sigma, j + 1, sm.h2, sm.c2, s, 0, h2buf);
-        wait_host(pl, s);   // h1, h2 and the flag are in pinned memory
+        // h1, h2 and the flag are in pinned memory
+        if (paradiag_status st = wait_host(pl, s); st != PD_OK) return st;
         skipped = *skiph != 0;
         if (defer && j == 0) {
           // beta = ||b|| from slot 2; V_0 = b and z_0, w carry the factor

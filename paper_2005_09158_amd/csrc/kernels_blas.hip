@@ -373,11 +373,13 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partia
   }
 }
 
-// The completion word of a solver round trip: written once every kernel
-// queued before this one has finished (their stores to the coherent pinned
-// buffer are then visible to the host, which polls the word).
+// The completion word of a solver round trip, stored once every kernel
+// queued before this one has finished.  The store is a release at system
+// scope (one vector store from one lane): the earlier kernels' writes to the
+// coherent pinned buffer are visible to the host before the word is, and the
+// host reads the word with acquire ordering.
 __global__ void k_signal(int* __restrict__ word, int v) {
-  if (threadIdx.x == 0) *word = v;
+  if (threadIdx.x == 0) __hip_atomic_store(word, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // dst[i] = src[i] for i < n: the solver's per-step scalars, staged by the

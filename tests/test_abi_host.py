@@ -62,12 +62,19 @@ def _setup(**kw):
     (dict(dim=1, ny=3), pd_lib.PD_ERR_INVALID),
     (dict(reserved=1), pd_lib.PD_ERR_INVALID),
     (dict(nu=1e-4), pd_lib.PD_ERR_UNSUPPORTED),    # cell Peclet number >= 1
+    (dict(prec=3), pd_lib.PD_ERR_UNSUPPORTED),     # single bf16 with a Schur basis
 ])
 def test_setup_rejects(kw, code):
     lib, st, h = _setup(**kw)
     assert st == code
     assert h.value is None
     assert len(lib.paradiag_last_error()) > 0
+
+
+def test_single_bf16_accepted_with_sine_basis():
+    lib, st, h = _setup(prec=3, ax=0.0)
+    assert st == pd_lib.PD_OK
+    lib.paradiag_destroy(h)
 
 
 def test_calls_without_workspace_fail_cleanly():

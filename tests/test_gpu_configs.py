@@ -1,23 +1,23 @@
 """Parity at the full sizes of the five workloads, in the launch configuration bench.py uses.
 
-Where the oracle can solve the whole problem in seconds it does (cfg1, cfg2,
-cfg4).  For the 512 x 512 workloads (cfg3 with 8 right-hand sides, cfg5 with
-2048 steps) two properties are checked instead:
-* the true relative residual ||b - A u|| / ||b||, with A applied by the oracle
-  (block-wise sparse products, exact definition) -- it must meet the solve's
-  tolerance;
-* the first time steps: A is block lower triangular, so U_1..U_k depend on
-  b_1..b_k only and the oracle's time stepper computes them exactly.
+The oracle solves every workload over its whole horizon by sequential float64
+time stepping (cfg3: right-hand side 0 of the 8; about half a minute of host
+time each for cfg3 and a minute for cfg5).  Every right-hand side of cfg3 also
+has its true relative residual ||b - A u|| / ||b|| formed by the oracle's
+block-wise product with A (the exact definition).
 Tolerances: float64 solves to rtol 1e-12 agree with the oracle to 1e-10
 (relative, max norm); mixed-precision solves meet rtol 1e-8 on the float64
-residual, and their distance to the oracle solution is bounded by the
-conditioning of A times that residual (checked at 1e-6).
+residual, and their relative 2-norm distance to the oracle solution is at most
+kappa_2(A) times that residual, with kappa_2(A) bounded from the structure of A
+(tests/bounds.py: 1.26e4 for cfg3, 1.87e6 for cfg5); cfg2 is checked at 1e-6
+in the max norm.
 """
 
 import numpy as np
 import pytest
 
 from oracle import Problem, adjoint as o_adj, operators as ops, rhs as o_rhs, solve as o_solve
+from tests.bounds import kappa2_bound
 from tests.gpu_util import announce, rel_err, torch_gpu
 from workloads import (CONFIGS, initial_state, initial_velocity, source_term, source_term_torch,
                        tracking_target, fd_directions)
@@ -81,18 +81,20 @@ def test_cfg2_full(prec):
     assert err < (1e-10 if prec == "fp64" else 1e-6)
 
 
-def _prefix_check(cfg, p, b_row, u_row, k):
-    """U_1..U_k of one right-hand side against the oracle's time stepper."""
-    pk = Problem.from_kwargs(**{**cfg.problem_kwargs(), "nt": k, "T": cfg.T * k / cfg.nt})
-    ref = o_solve.sequential(pk, b_row[:k])
-    return rel_err(u_row[:k], ref)
+def _full_error(p, b_row, u_row):
+    """Whole-horizon error of one right-hand side against the oracle's time stepper."""
+    ref = o_solve.sequential(p, b_row)
+    d = u_row - ref
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            float(np.abs(d).max() / np.abs(ref).max()))
 
 
+@pytest.mark.timeout(900)
 def test_cfg3_batch_mixed():
-    announce("cfg3 512x512x1024 batch 8 split-bf16, residual + prefix")
+    announce("cfg3 512x512x1024 batch 8 split-bf16, restart 8: residuals + whole-horizon error")
     torch = torch_gpu()
     cfg = CONFIGS["cfg3"]
-    pd = _pd(cfg, "fp32_bf16gemm", restart=4)
+    pd = _pd(cfg, "fp32_bf16gemm", restart=8)
     U0 = torch.from_numpy(initial_state(cfg)).cuda().reshape(1, cfg.ny, cfg.nx)
     U0 = U0.expand(cfg.batch, cfg.ny, cfg.nx).contiguous()
     f = torch.empty(pd.source_shape, dtype=torch.float64, device="cuda")
@@ -101,18 +103,27 @@ def test_cfg3_batch_mixed():
     b = pd.build_rhs(U0, None, f)
     del f
     u, res = pd.solve(b, rtol=cfg.rtol, max_iter=40)
-    print(f"  cfg3 iters {res.iters_per_rhs} resid {res.resid_per_rhs}")
+    print(f"  cfg3 iters {res.iters_per_rhs} resid {res.resid_per_rhs}", flush=True)
     assert res.converged and max(res.resid_per_rhs) <= cfg.rtol
-    # right-hand side 0 on the host: the oracle's own b, residual and first steps
+    bh = b.cpu().numpy().reshape(cfg.batch, cfg.nt, -1)
+    uh = u.cpu().numpy().reshape(cfg.batch, cfg.nt, -1)
+    del u, b, pd
+    torch.cuda.empty_cache()
     p, b0 = _rhs_np(cfg, 0)
-    assert rel_err(b[0].cpu().numpy().reshape(p.nt, -1), b0) < 1e-12
-    u0 = u[0].cpu().numpy().reshape(p.nt, -1)
-    del u, b
-    true_res = np.linalg.norm(b0 - ops.apply_A(p, u0)) / np.linalg.norm(b0)
-    err = _prefix_check(cfg, p, b0, u0, 16)
-    print(f"  cfg3 rhs0 true resid {true_res:.2e} first-16-steps err {err:.2e}")
-    assert true_res <= cfg.rtol * 1.01
-    assert err < 1e-6
+    # the GPU right-hand side 0 equals the oracle's
+    assert rel_err(bh[0], b0) < 1e-12
+    # every right-hand side meets the tolerance on the oracle's residual
+    true_res = []
+    for k in range(cfg.batch):
+        true_res.append(np.linalg.norm(bh[k] - ops.apply_A(p, uh[k])) / np.linalg.norm(bh[k]))
+    print(f"  cfg3 oracle true residuals {['%.2e' % r for r in true_res]}", flush=True)
+    assert max(true_res) <= cfg.rtol * 1.01
+    # right-hand side 0 against the oracle's solution over the whole horizon
+    kappa = kappa2_bound(cfg)
+    e2, emax = _full_error(p, b0, uh[0])
+    print(f"  cfg3 rhs0 whole-horizon error: 2-norm {e2:.2e} max-norm {emax:.2e} "
+          f"(bound kappa2 x residual = {kappa * true_res[0]:.2e})", flush=True)
+    assert e2 <= kappa * true_res[0] * 1.01
 
 
 def test_cfg4_gradient():
@@ -161,20 +172,24 @@ def test_cfg4_gradient():
     assert worst <= 1.0
 
 
+@pytest.mark.timeout(900)
 def test_cfg5_wave_fp32():
-    announce("cfg5 wave 512x512x2048 fp32 preconditioner, residual + prefix")
+    announce("cfg5 wave 512x512x2048 fp32 preconditioner: residual + whole-horizon error")
     torch = torch_gpu()
     cfg = CONFIGS["cfg5"]
     p, b = _rhs_np(cfg)
     pd = _pd(cfg, "fp32")
     bg = torch.from_numpy(b).reshape(pd.shape).cuda()
     u, res = pd.solve(bg, rtol=cfg.rtol, max_iter=60)
-    print(f"  cfg5 iters {res.iters} resid {res.rel_resid:.2e}")
+    print(f"  cfg5 iters {res.iters} resid {res.rel_resid:.2e}", flush=True)
     assert res.converged and res.rel_resid <= cfg.rtol
     un = u.cpu().numpy().reshape(p.nt, -1)
-    del u, bg
+    del u, bg, pd
+    torch.cuda.empty_cache()
     true_res = np.linalg.norm(b - ops.apply_A(p, un)) / np.linalg.norm(b)
-    err = _prefix_check(cfg, p, b, un, 16)
-    print(f"  cfg5 true resid {true_res:.2e} first-16-steps err {err:.2e}")
     assert true_res <= cfg.rtol * 1.01
-    assert err < 1e-6
+    kappa = kappa2_bound(cfg)
+    e2, emax = _full_error(p, b, un)
+    print(f"  cfg5 true resid {true_res:.2e} whole-horizon error: 2-norm {e2:.2e} max-norm "
+          f"{emax:.2e} (bound kappa2 x residual = {kappa * true_res:.2e})", flush=True)
+    assert e2 <= kappa * true_res * 1.01

@@ -10,10 +10,9 @@ Tolerances (relative, max-abs error over max-abs reference):
 * single bf16 x-transform: 5e-2 with the sine basis (u_bf16 = 3.9e-3 in each of the
   two transforms, amplified as above).  With a non-normal x factor the Schur
   basis carries that rounding through the back-substitution, whose coupling
-  norm ||T - diag T|| is of the order of ||K_x||; the measured error of
-  P_alpha^{-1} reaches 0.06 - 0.8 on these shapes, so the bound there is only
-  that the map stays a useful approximation (< 1).  Exactness of the solve
-  comes from flexible GMRES (test_fgmres_mixed_reaches_fp64_residual).
+  norm ||T - diag T|| is of the order of ||K_x||, and the error of
+  P_alpha^{-1} reached 0.06 - 0.8 on these shapes: setup refuses that
+  combination (PD_ERR_UNSUPPORTED), which the tests check.
 * matvec, right-hand side and its transpose: 1e-13 (a few float64 operations
   per entry, evaluated in a different order).
 * solves: 1e-10 against the sequential time stepper at rtol 1e-12.
@@ -40,7 +39,11 @@ CASES = {
 }
 
 PREC_TOL = {"fp64": 1e-11, "fp32": 2e-3, "fp32_bf16gemm": 2e-3, "fp32_bf16x1": 5e-2}
-BF16_SCHUR_TOL = 1.0
+
+
+def _bf16x1_schur(case, prec):
+    c = CASES[case]
+    return prec == "fp32_bf16x1" and c["dim"] == 2 and c.get("ax", 0.0) != 0.0
 
 
 def _shape(prob, batch=1):
@@ -51,6 +54,12 @@ def _shape(prob, batch=1):
 @pytest.mark.parametrize("case", list(CASES))
 def test_precond_parity(case, prec):
     announce(f"precond {case} {prec}")
+    if _bf16x1_schur(case, prec):
+        from paper_2005_09158_amd._lib import PD_ERR_UNSUPPORTED, ParaDiagError
+        with pytest.raises(ParaDiagError) as e:
+            make(CASES[case], prec)
+        assert e.value.status == PD_ERR_UNSUPPORTED
+        return
     torch, pd, prob = make(CASES[case], prec)
     r = np.random.default_rng(1).standard_normal((prob.nt, prob.nspace))
     z_ref = o_prec.three_steps(prob, r)
@@ -58,10 +67,7 @@ def test_precond_parity(case, prec):
     torch.cuda.synchronize()
     err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
     print(f"  rel err {err:.3e}")
-    tol = PREC_TOL[prec]
-    if prec == "fp32_bf16x1" and CASES[case]["dim"] == 2 and CASES[case].get("ax", 0.0) != 0.0:
-        tol = BF16_SCHUR_TOL
-    assert err < tol
+    assert err < PREC_TOL[prec]
 
 
 # Back-sweep shapes: every line-segment width of the one-wave scan (rows per
@@ -86,9 +92,11 @@ def test_schur_sweep_shapes(nx, ny, prec):
 
 
 # Line-solver shapes (sine basis): lines of 256 .. 512 rows take 8 rows per
-# lane (32 or 64 lanes per line), a ragged length pads the last lane, and an
-# x-size that is not a multiple of 4 takes the element-wise tile copies.
-LINE_SHAPES = [(8, 256), (6, 300), (4, 512), (5, 129)]
+# lane (32 or 64 lanes per line), 1024 and 2048 rows take 16 and 32 rows per
+# lane (tiles of 4 modes; 135 KiB of LDS at 2048 rows in float64), a ragged
+# length pads the last lane, and an x-size that is not a multiple of 4 takes
+# the element-wise tile copies.
+LINE_SHAPES = [(8, 256), (6, 300), (4, 512), (5, 129), (4, 1024), (3, 2048), (5, 1500)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -109,8 +117,10 @@ def test_line_solver_shapes(nx, ny, prec):
 # Time-FFT shapes: on a 16 x 8 grid (sine basis) these Nt select the
 # four-step kernels with pencil lengths 4 .. 32 and tiles of 32, 16 and 8
 # columns (Nt = 2048 in float32, and Nt = 512 and 1024 in float64, take the
-# 512-thread workgroups), and the Stockham kernel below them.
-FFT_NT = {"fp32": [16, 64, 128, 256, 512, 2048], "fp64": [16, 64, 256, 512, 1024]}
+# 512-thread workgroups), and the Stockham kernel below them and above them
+# (Nt = 4096, and Nt = 2048 in float64: one complex column per workgroup,
+# 98 KiB of LDS at Nt = 4096 in float64).
+FFT_NT = {"fp32": [16, 64, 128, 256, 512, 2048, 4096], "fp64": [16, 64, 256, 512, 1024, 2048, 4096]}
 
 
 @pytest.mark.parametrize("prec,nt", [(p, n) for p, ns in FFT_NT.items() for n in ns])
@@ -202,6 +212,8 @@ def test_fgmres_fp64_matches_sequential(case):
 @pytest.mark.parametrize("case", ["1d-be", "2d-tr-schur", "2d-lf-dst", "2d-be-schur-64"])
 def test_fgmres_mixed_reaches_fp64_residual(case, prec):
     announce(f"fgmres {prec} {case}")
+    if _bf16x1_schur(case, prec):
+        pytest.skip("single-bf16 x-transform is refused with a Schur basis (see test_precond_parity)")
     torch, pd, prob = make(CASES[case], prec)
     b = np.random.default_rng(6).standard_normal((prob.nt, prob.nspace))
     u, res = pd.solve(to_gpu(torch, b, pd.shape), rtol=1e-10, max_iter=60)
