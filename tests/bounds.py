@@ -56,3 +56,30 @@ def kappa2_bound(cfg):
             raise ValueError("the leap-frog bound needs a symmetric K")
         return (4.0 / cfg.dt ** 2 + K) * _lf_inverse_norm(cfg)
     raise ValueError(cfg.scheme)
+
+
+def line_condition(params):
+    """2-norm condition number of the worst Step-(b) system of a problem whose
+    spatial operator is symmetric (sine basis in x, y lines): in the joint sine
+    eigenbasis every system (lambda1_n I + lambda2_n K) is diagonal with
+    entries lambda1_n + lambda2_n (t_k + mu_j), so its condition is the ratio
+    of the largest to the smallest modulus over j, maximised over the
+    frequencies n and x-modes k.  A backward-stable line solve has a forward
+    error of order u times this number."""
+    from oracle import Problem, operators as ops
+    p = Problem.from_kwargs(**params)
+    if params.get("ax", 0.0) != 0.0 or params.get("ay", 0.0) != 0.0:
+        raise ValueError("line_condition needs a symmetric spatial operator")
+    lam1, lam2 = ops.time_symbols(p)
+
+    def eig(n):
+        h = 1.0 / (n + 1)
+        return 4.0 * params["nu"] / h ** 2 * np.sin(np.arange(1, n + 1) * np.pi / (2 * (n + 1))) ** 2
+
+    tx = eig(params["nx"]) if params["dim"] == 2 else np.zeros(1)
+    my = eig(params["ny"] if params["dim"] == 2 else params["nx"])
+    worst = 0.0
+    for a, b in zip(lam1, lam2):
+        ev = np.abs(a + b * (tx[:, None] + my[None, :]))
+        worst = max(worst, float(np.max(ev.max(axis=1) / ev.min(axis=1))))
+    return worst

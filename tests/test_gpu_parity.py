@@ -23,6 +23,7 @@ import pytest
 
 from oracle import adjoint as o_adj, operators as ops, precond as o_prec, rhs as o_rhs, solve as o_solve
 from tests.gpu_util import announce, make, rel_err, to_gpu
+from tests.bounds import line_condition
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +40,7 @@ CASES = {
 }
 
 PREC_TOL = {"fp64": 1e-11, "fp32": 2e-3, "fp32_bf16gemm": 2e-3, "fp32_bf16x1": 5e-2}
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
 
 
 def _bf16x1_schur(case, prec):
@@ -110,8 +112,11 @@ def test_line_solver_shapes(nx, ny, prec):
     z = pd.apply_precond(to_gpu(torch, r, pd.shape))
     torch.cuda.synchronize()
     err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
-    print(f"  rel err {err:.3e}")
-    assert err < PREC_TOL[prec]
+    # long lines are ill-conditioned (the condition grows as ny^2): a
+    # backward-stable elimination leaves an error of order u times it
+    tol = max(PREC_TOL[prec], 4 * UNIT_ROUNDOFF[prec] * line_condition(cfg))
+    print(f"  rel err {err:.3e} tol {tol:.2e}")
+    assert err < tol
 
 
 # Time-FFT shapes: on a 16 x 8 grid (sine basis) these Nt select the
