@@ -22,4 +22,4 @@ Parity status of every function is stated in its module docstring.
 """
 
 from .problem import Problem  # noqa: F401
-from . import operators, rhs, solve, precond, krylov, adjoint  # noqa: F401
+from . import operators, rhs, solve, precond, krylov, adjoint, hybrid  # noqa: F401

@@ -17,4 +17,6 @@ from .fields import (  # noqa: F401
     tracking_target,
     fd_directions,
     random_vector,
+    hybrid_wave_data,
+    hybrid_wave_exact,
 )

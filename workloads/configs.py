@@ -12,6 +12,10 @@ consumer assembles its own operators from them.
 * ``cfg4``  2D advection-diffusion, 128^2, backward Euler, Nt = 256
             (gradient of a tracking cost through the adjoint solve).
 * ``cfg5``  2D wave equation, 512^2, implicit leap-frog, Nt = 2048, T = 2.
+* ``hyb``   2D wave equation u_tt = Laplacian u + f on the 511^2 interior
+            points of mesh width 1/512, T = 2, Nt = 512, hybrid time
+            discretisation solved directly (ParaDiag-I; the problem of Table
+            Ex2Tab1, whose exact solution is x(x-1) y(y-1) sin(2 pi t)).
 """
 
 from __future__ import annotations
@@ -27,7 +31,8 @@ class Config:
     nx: int             # interior points along x
     ny: int             # interior points along y (1 when dim == 1)
     nt: int             # number of time steps
-    scheme: str         # 'be' (backward Euler), 'tr' (trapezoidal), 'lf' (implicit leap-frog)
+    scheme: str         # 'be' (backward Euler), 'tr' (trapezoidal), 'lf' (implicit leap-frog),
+                        # 'hyb' / 'hyb2' (hybrid midpoint + backward Euler, first / second order)
     T: float            # final time; dt = T / nt
     nu: float           # diffusion coefficient (c^2 for the wave equation)
     ax: float           # velocity, x component (0 for the wave equation)
@@ -72,6 +77,8 @@ CONFIGS = {
                    rtol=1e-12, prec="fp64", with_source=True, beta=1e-4, seed=101),
     "cfg5": Config("cfg5", 2, 512, 512, 2048, "lf", 2.0, 1.0, 0.0, 0.0, 1e-2,
                    rtol=1e-8, prec="fp32"),
+    "hyb": Config("hyb", 2, 511, 511, 512, "hyb2", 2.0, 1.0, 0.0, 0.0, 1.0,
+                  rtol=1e-8, prec="fp64", with_source=True),
 }
 
 

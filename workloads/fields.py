@@ -136,3 +136,27 @@ def random_vector(shape, seed: int, low: float = -1.0, high: float = 1.0) -> np.
     """Uniform random float64 array used as a generic all-at-once test vector."""
     rng = np.random.default_rng(seed)
     return rng.uniform(low, high, size=shape)
+
+
+def hybrid_wave_data(cfg: Config):
+    """Data of the wave problem of Table Ex2Tab1 on the workload's grid:
+    u_tt - Laplacian u = f on (0,1)^2 with u = 0 on the boundary,
+    u(0) = 0, u_t(0) = 2 pi phi, phi = x(x-1) y(y-1), and
+    f = -4 pi^2 phi sin(2 pi t) - 2 sin(2 pi t) (x(x-1) + y(y-1)).
+    Returns (U0 [ny][nx], V0 [ny][nx], f [nt+1][ny][nx] at t_0 .. t_nt)."""
+    x, y = _grids(cfg)
+    gx, gy = x * (x - 1.0), y * (y - 1.0)
+    phi = np.outer(gy, gx)
+    lap = np.add.outer(gy, gx)
+    t = np.arange(cfg.nt + 1, dtype=np.float64) * cfg.dt
+    s = np.sin(2.0 * np.pi * t)
+    f = s[:, None, None] * (-4.0 * np.pi ** 2 * phi - 2.0 * lap)[None]
+    return np.zeros_like(phi), 2.0 * np.pi * phi, f
+
+
+def hybrid_wave_exact(cfg: Config) -> np.ndarray:
+    """Exact solution x(x-1) y(y-1) sin(2 pi t_n) at t_1 .. t_nt, [nt][ny][nx]."""
+    x, y = _grids(cfg)
+    phi = np.outer(y * (y - 1.0), x * (x - 1.0))
+    t = np.arange(1, cfg.nt + 1, dtype=np.float64) * cfg.dt
+    return np.sin(2.0 * np.pi * t)[:, None, None] * phi[None]
