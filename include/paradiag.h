@@ -30,7 +30,9 @@
  *   obtained from any allocator, e.g. PyTorch's).  A plan owns host tables
  *   and, from its first solve on, a small pinned host buffer for the solvers'
  *   per-step scalars (freed by paradiag_destroy); its device tables live
- *   inside the bound workspace.  The library allocates no device memory.  A
+ *   inside the bound workspace.  The library allocates no device memory at
+ *   run time; its code object holds one static array per device, used only by
+ *   paradiag_apply_precond_static.  A
  *   plan is not thread-safe, and two solves with one plan must not overlap
  *   in time, even on different streams (they share that buffer).
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Every
@@ -167,6 +169,24 @@ paradiag_status paradiag_matvec(paradiag_plan plan, const double* u, double* y, 
  * preconditioner precision (input and output float64).  z == r allowed. */
 paradiag_status paradiag_apply_precond(paradiag_plan plan, const double* r, double* z,
                                        void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): z =
+ * P_alpha^{-1} r computed exactly as by paradiag_apply_precond (same kernels,
+ * same arithmetic), but with the two spectral buffers of Step-(a)..(c) in a
+ * static device array of PD_STATIC_SCRATCH_BYTES per device instead of the
+ * bound workspace.  The call allocates nothing (no hipMalloc, hipFree or
+ * event creation) and records no stage timing.  The plan must still be bound
+ * (its tables live in the workspace).  Limit: twice the plan's spectral buffer
+ * (batch * (nt/2+1) * nx * ny complex values in the preconditioner precision,
+ * 256-byte aligned) must fit in PD_STATIC_SCRATCH_BYTES, else
+ * PD_ERR_WORKSPACE.  The array is shared by every call on one GPU and keeps
+ * the last call's contents (no call relies on it starting at zero): calls that
+ * overlap in time on one GPU, with any plans and on any streams, race.
+ * z == r allowed. */
+#define PD_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+paradiag_status paradiag_apply_precond_static(paradiag_plan plan, const double* r, double* z,
+                                              void* stream);
 
 /* Solve A u = b per opts->mode.  u: in = initial guess if opts->use_x0,
  * out = solution.  Returns PD_NOT_CONVERGED (u = last iterate) when max_iter

@@ -16,6 +16,7 @@ PD_ERR_WORKSPACE = -3
 PD_ERR_HIP = -4
 PD_ERR_NONFINITE = -5
 PD_ERR_BREAKDOWN = -6
+PD_STATIC_SCRATCH_BYTES = 128 << 20
 
 STATUS_NAMES = {0: "PD_OK", 1: "PD_NOT_CONVERGED", -1: "PD_ERR_INVALID", -2: "PD_ERR_UNSUPPORTED",
                 -3: "PD_ERR_WORKSPACE", -4: "PD_ERR_HIP", -5: "PD_ERR_NONFINITE",
@@ -61,6 +62,7 @@ SIGNATURES = {
     "paradiag_rhs_transpose": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "paradiag_matvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     "paradiag_apply_precond": (ctypes.c_int, [_P, _P, _P, _P]),
+    "paradiag_apply_precond_static": (ctypes.c_int, [_P, _P, _P, _P]),
     "paradiag_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "paradiag_adjoint_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "paradiag_get_xbasis": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D]),

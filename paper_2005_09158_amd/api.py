@@ -126,6 +126,16 @@ class ParaDiag:
                    "paradiag_apply_precond")
         return z
 
+    def apply_precond_static(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """paradiag_apply_precond_static: the same z = P^{-1} r with the spectral
+        buffers in the library's static device array (the call allocates nothing;
+        `out` must then be given by a caller that cannot allocate)."""
+        z = out if out is not None else torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.paradiag_apply_precond_static(self.plan, _ptr(r, self.shape, "r"),
+                                                          _ptr(z, self.shape, "z"), _stream()),
+                   "paradiag_apply_precond_static")
+        return z
+
     def _solve(self, fn, name, b, u, mode, rtol, max_iter, restart, x0):
         if mode is None:
             mode = self.mode

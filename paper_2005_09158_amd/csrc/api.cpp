@@ -325,26 +325,30 @@ static double sweep_flops(const Plan& pl) {
   return 8.0 * g.B * g.F * g.sy * 0.5 * (double)g.sx * (g.sx - 1);
 }
 
-// bscale: per right-hand side factor on the input (entry b * bstride), or null
+// bscale: per right-hand side factor on the input (entry b * bstride), or null.
+// buf_a, buf_b: the two spectral buffers (null: the plan's, in the bound workspace).
 static void apply_prec(Plan& pl, int variant, const double* in, const double* bscale, int bstride,
-                       void* out, bool out_f32, int accumulate, hipStream_t s) {
+                       void* out, bool out_f32, int accumulate, hipStream_t s,
+                       void* buf_a = nullptr, void* buf_b = nullptr) {
   const SpaceOp& op = pl.op[variant];
+  void* const spec_a = buf_a ? buf_a : pl.spec_a;
+  void* const spec_b = buf_b ? buf_b : pl.spec_b;
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
-  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, bstride, pl.spec_a, variant, s); }
+  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, bstride, spec_a, variant, s); }
   if (pl.p.dim == 2) {
-    { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, pl.spec_a, pl.spec_b, s); }
+    { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, spec_a, spec_b, s); }
     {
       Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, pl.schur ? sweep_flops(pl) : 0.0);
-      if (pl.schur) schur_sweep(pl, op, pl.spec_b, s);
-      else line_solve(pl, op, pl.spec_b, s);
+      if (pl.schur) schur_sweep(pl, op, spec_b, s);
+      else line_solve(pl, op, spec_b, s);
     }
-    { Timed t(pl, PD_STAGE_XFORM_INV, s, 2 * sb, xform_flops(pl)); xform(pl, op, false, pl.spec_b, pl.spec_a, s); }
+    { Timed t(pl, PD_STAGE_XFORM_INV, s, 2 * sb, xform_flops(pl)); xform(pl, op, false, spec_b, spec_a, s); }
   } else {
     Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, 0.0);
-    line_solve(pl, op, pl.spec_a, s);
+    line_solve(pl, op, spec_a, s);
   }
-  { Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, fft_flops(pl)); fft_time_inverse(pl, pl.spec_a, out, out_f32, accumulate, variant, s); }
+  { Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, fft_flops(pl)); fft_time_inverse(pl, spec_a, out, out_f32, accumulate, variant, s); }
 }
 
 // y = b - A u (A u without b); with `sq`, also the partial sums of y . y, one
@@ -1201,3 +1205,26 @@ paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t
 }
 
 }  // extern "C"
+
+// z = P_alpha^{-1} r with the spectral buffers at spec_a, spec_b (each spec_bytes
+// long) instead of the bound workspace's; used by the allocation-free entry point.
+paradiag_status pd::apply_precond_into(paradiag_plan plan, const double* r, double* z, void* spec_a,
+                                   void* spec_b, size_t spec_bytes, hipStream_t s) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!r || !z) { set_error("NULL vector"); return PD_ERR_INVALID; }
+  size_t nb = sizeof(double) * (size_t)pl->g.NA;
+  if (r != z && overlap(r, nb, z, nb)) { set_error("r and z partially overlap"); return PD_ERR_INVALID; }
+  const size_t need = align_up((size_t)pl->g.spec_elems * spec_elem_bytes(pl->prec));
+  if (spec_bytes < need) {
+    set_error("spectral buffers of this plan (" + std::to_string(2 * need) +
+              " bytes) exceed the static scratch (" + std::to_string(2 * spec_bytes) + " bytes)");
+    return PD_ERR_WORKSPACE;
+  }
+  // no stage timing here: recording events may create them
+  const bool timing = pl->timer.enabled;
+  pl->timer.enabled = false;
+  apply_prec(*pl, 0, r, nullptr, 0, z, false, 0, s, spec_a, spec_b);
+  pl->timer.enabled = timing;
+  return check_hip("apply_precond_static");
+}

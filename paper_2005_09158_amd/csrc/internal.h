@@ -146,6 +146,10 @@ size_t spec_elem_bytes(Prec p);          // 8 (double) or 4 (float)
 size_t tables_bytes(const Plan& pl);     // device tables + spectral buffers
 size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o);
 void set_error(const std::string& msg);
+// z = P_alpha^{-1} r (paradiag_apply_precond) with caller-supplied spectral
+// buffers of spec_bytes each in place of the bound workspace's; no stage timing.
+paradiag_status apply_precond_into(paradiag_plan plan, const double* r, double* z, void* spec_a,
+                                   void* spec_b, size_t spec_bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- kernels
 struct Launch { hipStream_t stream; };
