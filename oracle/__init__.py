@@ -17,9 +17,14 @@ What it computes, all in float64, each function citing the passage it follows:
   alpha-circulant matrix (eq1.2) and the three FFT steps (eq1.3 / eq2.12).
 * ``krylov``     flexible GMRES and the stationary iteration (eq5.1).
 * ``adjoint``    the transposed solve and the gradient of a tracking cost.
+* ``hybrid``     ParaDiag-I with the hybrid midpoint / backward Euler time
+  discretisation (Section 2.1.2): its time matrices, the closed-form
+  eigendecomposition and exact all-at-once solves.
+* ``parareal``   classical parareal and the ParaDiag-II parareal variant with
+  the alpha-periodic coarse-grid correction (Section 2.2.2).
 
 Parity status of every function is stated in its module docstring.
 """
 
 from .problem import Problem  # noqa: F401
-from . import operators, rhs, solve, precond, krylov, adjoint, hybrid  # noqa: F401
+from . import operators, rhs, solve, precond, krylov, adjoint, hybrid, parareal  # noqa: F401
