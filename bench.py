@@ -23,6 +23,10 @@ The JSON line also carries
   (one core; it also yields the error reference), and a sample of the
   oracle's own ParaDiag-II preconditioner with Step-(b) spread over the host
   cores, scaled to a whole solve.
+* a ParaDiag-I leg (key `paradiag_i`): the direct float64 solve of the hybrid
+  time discretisation on the wave problem of Table Ex2Tab1 (511^2 x 512), its
+  rate, its error against the exact solution and its dominant kernel's
+  roofline.
 One extra solve before the timed region, with every stage timed, gives the
 per-stage breakdown and picks the dominant stage; inside the timed region only
 that stage records events, since every event pair costs a few microseconds of
@@ -69,6 +73,8 @@ def parse():
                          "for the wave equation, split-bf16 x-transform otherwise)")
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-paradiag-i", action="store_true",
+                    help="skip the ParaDiag-I (hybrid time discretisation) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle's sequential solve (no error_vs_oracle, no cpu_baseline)")
@@ -319,6 +325,66 @@ def cpu_baselines(cfg, ref_dt, sample, iters):
     return base, para
 
 
+def run_paradiag_i(args, torch):
+    """ParaDiag-I leg: the direct solve of the hybrid time discretisation on the
+    wave problem of Table Ex2Tab1 (511^2 points, Nt = 512, T = 2), float64,
+    with the right-hand side resident in HBM.  Reports unknowns/s of whole
+    direct solves (time transforms with V^{-1} and V, Step-(b), and the
+    residual check), the error against the exact solution (the table prints
+    7.88e-05), and the roofline of the dominant kernel."""
+    from paper_2005_09158_amd import ParaDiag
+    from workloads import CONFIGS, hybrid_wave_data, hybrid_wave_exact
+    cfg = CONFIGS["hyb"]
+    pd = ParaDiag(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, scheme=cfg.scheme, T=cfg.T, nu=cfg.nu,
+                  alpha=cfg.alpha, batch=cfg.batch, prec="fp64", mode="direct")
+    U0, V0, f = hybrid_wave_data(cfg)
+    b = pd.build_rhs(torch.from_numpy(U0).reshape(pd.field_shape).cuda(),
+                     torch.from_numpy(V0).reshape(pd.field_shape).cuda(),
+                     torch.from_numpy(f).reshape(pd.source_shape).cuda())
+    u = torch.empty_like(b)
+    for _ in range(args.warmup):
+        pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
+    pd.set_timing(True)
+    pd.stage_times(reset=True)
+    pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
+    stages = pd.stage_times(reset=True)
+    dominant = max(stages, key=lambda k: stages[k][0])
+    pd.set_timing(True, stages=[dominant])
+    pd.stage_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res = pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    timed = pd.stage_times(reset=True)
+    pd.set_timing(False)
+    un = u.cpu().numpy().reshape(cfg.nt, -1)
+    err = float(np.abs(un - hybrid_wave_exact(cfg).reshape(cfg.nt, -1)).max())
+    tms, cnt, by, fl = timed[dominant]
+    avg_s = tms / 1e3 / max(cnt, 1)
+    bound = "mfma" if dominant in ("fft_fwd", "fft_inv", "xform_fwd", "xform_inv") else "hbm"
+    if bound == "mfma":
+        achieved, peak, unit = fl / max(cnt, 1) / avg_s / 1e12, PEAK["mfma_TFs"]["fp64"], "TFLOP/s"
+    else:
+        achieved, peak, unit = by / max(cnt, 1) / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
+    kernel = {"fft_fwd": "k_time_gemm (V^-1)", "fft_inv": "k_time_gemm (V)"}.get(dominant, STAGE_KERNEL[dominant])
+    U = cfg.unknowns
+    return {
+        "workload": f"hyb: 2D wave equation {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, T {cfg.T}, hybrid "
+                    f"midpoint/backward-Euler time discretisation, direct ParaDiag-I solve (Table Ex2Tab1)",
+        "unknowns": U, "ms_per_step": ms, "value": U / (ms / 1e3), "unit": "unknowns/s",
+        "dtype": "f64", "rel_resid": res.rel_resid,
+        "error_vs_exact": err, "error_printed_in_paper": 7.88e-05,
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
+        "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 4), "kernel": kernel, "stage": dominant,
+                     "launches": cnt, "avg_launch_ms": round(tms / max(cnt, 1), 5),
+                     "algorithmic_flops_per_launch": fl / max(cnt, 1),
+                     "algorithmic_bytes_per_launch": by / max(cnt, 1)},
+    }
+
+
 def workload_name(cfg):
     if cfg.dim == 1:
         return (f"{cfg.name}: 1D advection-diffusion {cfg.nx} points, Nt {cfg.nt}, "
@@ -411,6 +477,11 @@ def main():
             line["cpu_baseline"] = base
             if para:
                 line["cpu_baseline_paradiag_ii"] = para
+    if not args.skip_paradiag_i:
+        print("[bench] ParaDiag-I leg (hybrid wave, 511^2 x 512)", file=sys.stderr, flush=True)
+        line["paradiag_i"] = run_paradiag_i(args, torch)
+        print(f"[bench] ParaDiag-I: {line['paradiag_i']['ms_per_step']:.3f} ms/solve error vs exact "
+              f"{line['paradiag_i']['error_vs_exact']:.3e}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

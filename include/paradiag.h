@@ -68,7 +68,20 @@ typedef enum {
   PD_ERR_BREAKDOWN = -6     /* singular pivot in setup or a Krylov breakdown */
 } paradiag_status;
 
-typedef enum { PD_BE = 0, PD_TR = 1, PD_LEAPFROG = 2 } paradiag_scheme;
+/* PD_HYBRID, PD_HYBRID_WAVE: ParaDiag-I with the hybrid time discretisation
+ * of Section 2.1.2 (explicit midpoint for the first Nt - 1 steps, backward
+ * Euler for the last, neq2.9a).  The all-at-once matrix is A = B (x) I + I (x) K
+ * (neq2.9b, B of neq2.9c) for u' + K u = f, and A = B^2 (x) I + I (x) K
+ * (neq2.15) for the second-order problem u'' + K u = f with the velocity
+ * eliminated.  B = V D V^{-1} in closed form (Thm thmCondU), so
+ * paradiag_apply_precond computes A^{-1} r exactly (up to rounding): Step-(a)
+ * and Step-(c) are dense float64 products with V^{-1} and V on MFMA instead of
+ * FFTs, Step-(b) solves (d_n I + K) per eigenvalue d_n of B (or B^2).  alpha
+ * is unused; nt must be even (any even value in [4, 4096]).  Supported: matvec
+ * (and its transpose), build_rhs, apply_precond, solve in PD_MODE_DIRECT and
+ * PD_MODE_STATIONARY (iterative refinement; one step suffices in float64);
+ * PD_MODE_FGMRES, adjoint_solve and rhs_transpose return PD_ERR_UNSUPPORTED. */
+typedef enum { PD_BE = 0, PD_TR = 1, PD_LEAPFROG = 2, PD_HYBRID = 3, PD_HYBRID_WAVE = 4 } paradiag_scheme;
 
 /* Arithmetic of the preconditioner.  The all-at-once residual, the matvec,
  * the Krylov vectors, the Arnoldi process and the alpha-scaling tables are
@@ -96,7 +109,7 @@ typedef struct {
   int32_t dim;        /* 1 or 2 */
   int32_t nx, ny;     /* interior points per direction; ny = 1 when dim = 1; nx, ny in [1, 2048]
                        (nx <= 1024 when ax != 0: host Schur cost) */
-  int32_t nt;         /* time steps: a power of two in [4, 4096] */
+  int32_t nt;         /* time steps: a power of two in [4, 4096] (hybrid schemes: even, [4, 4096]) */
   int32_t batch;      /* independent right-hand sides, 1..64 */
   int32_t scheme;     /* paradiag_scheme */
   int32_t prec;       /* paradiag_prec */
@@ -148,10 +161,13 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
                                         void* stream);
 
 /* b = all-at-once right-hand side from U0, the initial velocity u1 (leap-frog
- * only; NULL = 0) and the source f (NULL = 0).  theta-method: b_1 =
- * (I/dt - (1-theta)K)U0 + theta f_1 + (1-theta) f_0, b_n = theta f_n +
- * (1-theta) f_{n-1} (eq2.5 with a source); leap-frog: first two rows from
- * the scheme at t_0 with a central ghost value (eq3.2). */
+ * and PD_HYBRID_WAVE only; NULL = 0) and the source f (NULL = 0).
+ * theta-method: b_1 = (I/dt - (1-theta)K)U0 + theta f_1 + (1-theta) f_0,
+ * b_n = theta f_n + (1-theta) f_{n-1} (eq2.5 with a source); leap-frog: first
+ * two rows from the scheme at t_0 with a central ghost value (eq3.2).
+ * PD_HYBRID: b_n = f_n, plus U0/(2 dt) in row 1 (neq2.9c); PD_HYBRID_WAVE:
+ * b_n = f_n, plus u1/(2 dt) in row 1 and -U0/(4 dt^2) in row 2 (the first-order
+ * system neq2.14b with the velocity eliminated). */
 paradiag_status paradiag_build_rhs(paradiag_plan plan, const double* U0, const double* u1,
                                    const double* f, double* b, void* stream);
 
@@ -209,7 +225,9 @@ paradiag_status paradiag_adjoint_solve(paradiag_plan plan, const double* g, doub
 paradiag_status paradiag_get_xbasis(paradiag_plan plan, int32_t adjoint, double* q, double* t);
 
 /* Copy the host time symbols lambda_1, lambda_2 for n = 0..nt/2 (interleaved
- * complex float64, nt/2+1 values each).  Host only. */
+ * complex float64, nt/2+1 values each).  Hybrid schemes: the nt/2 eigenvalues
+ * d_n of B (or B^2) with Re(x_n) > 0 in lambda_1 (the others are their
+ * conjugates) and 1 in lambda_2.  Host only. */
 paradiag_status paradiag_get_symbols(paradiag_plan plan, double* lam1, double* lam2);
 
 /* Stage timing.  When enabled, every later call records HIP events around

@@ -20,7 +20,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libparadiag.so")
 
 SOURCES = ["api.cpp", "schur.cpp", "kernels_fft.hip", "kernels_tri.hip", "kernels_sweep.hip", "kernels_gemm.hip",
-           "kernels_blas.hip", "static_scratch.hip"]
+           "kernels_blas.hip", "static_scratch.hip", "hybrid.cpp",
+           "kernels_hybrid.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

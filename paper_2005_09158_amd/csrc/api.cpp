@@ -87,10 +87,15 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
       !std::isfinite(p.ax) || !std::isfinite(p.ay)) {
     set_error("T and nu must be positive and finite"); return PD_ERR_INVALID;
   }
-  if (p.scheme < 0 || p.scheme > 2) { set_error("unknown scheme"); return PD_ERR_INVALID; }
+  if (p.scheme < 0 || p.scheme > 4) { set_error("unknown scheme"); return PD_ERR_INVALID; }
+  const bool hybrid = p.scheme == PD_HYBRID || p.scheme == PD_HYBRID_WAVE;
   if (p.prec < 0 || p.prec > 3) { set_error("unknown precision"); return PD_ERR_INVALID; }
   if (p.reserved != 0) { set_error("reserved must be 0"); return PD_ERR_INVALID; }
-  if (!is_pow2(p.nt) || p.nt < 4 || p.nt > 4096) {
+  if (hybrid) {
+    if ((p.nt & 1) || p.nt < 4 || p.nt > 4096) {
+      set_error("hybrid schemes need an even nt in [4, 4096]"); return PD_ERR_UNSUPPORTED;
+    }
+  } else if (!is_pow2(p.nt) || p.nt < 4 || p.nt > 4096) {
     set_error("nt must be a power of two in [4, 4096]"); return PD_ERR_UNSUPPORTED;
   }
   if (p.dim == 1 && p.nx > 2048) { set_error("nx > 2048 unsupported in 1D"); return PD_ERR_UNSUPPORTED; }
@@ -115,7 +120,7 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
   pl->p = p;
   pl->prec = static_cast<Prec>(p.prec);
   Geom& g = pl->g;
-  g.B = p.batch; g.nt = p.nt; g.F = p.nt / 2 + 1;
+  g.B = p.batch; g.nt = p.nt; g.F = hybrid ? p.nt / 2 : p.nt / 2 + 1;
   g.nx = p.nx; g.ny = p.ny;
   if (p.dim == 2) { g.sx = p.nx; g.sy = p.ny; } else { g.sx = 1; g.sy = p.nx; }
   g.S = (int64_t)p.nx * p.ny;
@@ -124,11 +129,30 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
   g.spec_elems = (int64_t)g.B * g.F * g.sy * 2 * g.sx;
 
   const double dt = p.T / p.nt;
+  const double PI = 3.14159265358979323846;
+  if (hybrid) {
+    // ParaDiag-I: the closed-form eigendecomposition of B (Thm thmCondU)
+    pl->hybrid = true;
+    pl->order = p.scheme == PD_HYBRID ? 1 : 2;
+    HybridTables ht;
+    std::string err;
+    if (!hybrid_eigen(p.nt, dt, pl->order, ht, err)) { set_error(err); return PD_ERR_BREAKDOWN; }
+    pl->lam1 = ht.d;
+    pl->lam2.assign(g.F, cd(1.0, 0.0));
+    pl->wf_frag = time_gemm_fragments(ht.wf, p.nt);
+    pl->wi_frag = time_gemm_fragments(ht.wi, p.nt);
+    pl->band = ht.band;
+    pl->band_t.assign(ht.band.size(), 0.0);   // rows of the transpose: (B^T)[r][r+k] = B[r+k][r]
+    for (int r = 0; r < p.nt; ++r)
+      for (int k = -2; k <= 2; ++k)
+        if (r + k >= 0 && r + k < p.nt) pl->band_t[(size_t)r * 5 + k + 2] = ht.band[(size_t)(r + k) * 5 - k + 2];
+    pl->L = 1;
+    pl->theta = 1.0;
+  } else {
   time_columns(p.scheme, dt, pl->c1, pl->c2, &pl->L, &pl->theta);
 
   // time symbols lambda_j(n) = sum_k c_jk z_n^k, z_n = alpha^{1/Nt} e^{-2 pi i n/Nt}
   // (the Fourier transform of Gamma_alpha c_j, Lemma 1)
-  const double PI = 3.14159265358979323846;
   double r = std::pow(p.alpha, 1.0 / p.nt);
   pl->lam1.resize(g.F);
   pl->lam2.resize(g.F);
@@ -143,6 +167,7 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
     pl->lam1[n] = s1;
     pl->lam2[n] = s2;
   }
+  }  // not hybrid
   pl->gam.resize(p.nt);
   pl->invgam.resize(p.nt);
   double la = std::log(p.alpha);
@@ -210,6 +235,10 @@ size_t tables_bytes(const Plan& pl) {
   b += align_up(sizeof(double2) * g.nt);              // twiddles f64
   b += align_up(sizeof(float2) * g.nt);               // twiddles f32
   b += align_up(sizeof(double2) * 2 * g.F);           // lam
+  if (pl.hybrid) {
+    b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt));   // V^{-1}, V (fragment order)
+    b += 2 * align_up(sizeof(double) * 5 * g.nt);                         // banded rows of B, B^T
+  }
   if (pl.p.dim == 2) {
     const size_t n = g.nx;
     size_t gm = pl.schur ? (2 * n) * (2 * n) : n * n;
@@ -314,6 +343,10 @@ static double fft_flops(const Plan& pl) {
   double lg = std::log2((double)pl.g.nt);
   return 5.0 * pl.g.nt * lg * (pl.g.NA / (double)pl.g.nt) * 0.5;
 }
+static double time_flops(const Plan& pl) {
+  if (pl.hybrid) return 2.0 * pl.g.nt * (double)pl.g.NA;   // two dense nt x nt products per point
+  return fft_flops(pl);
+}
 static double xform_flops(const Plan& pl) {
   const Geom& g = pl.g;
   double rows = (double)g.B * g.F * g.sy;
@@ -335,7 +368,11 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   void* const spec_b = buf_b ? buf_b : pl.spec_b;
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
-  { Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, fft_flops(pl)); fft_time_forward(pl, in, bscale, bstride, spec_a, variant, s); }
+  {
+    Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, time_flops(pl));
+    if (pl.hybrid) time_transform(pl, true, in, spec_a, false, 0, s);
+    else fft_time_forward(pl, in, bscale, bstride, spec_a, variant, s);
+  }
   if (pl.p.dim == 2) {
     { Timed t(pl, PD_STAGE_XFORM_FWD, s, 2 * sb, xform_flops(pl)); xform(pl, op, true, spec_a, spec_b, s); }
     {
@@ -348,7 +385,11 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
     Timed t(pl, PD_STAGE_LINE_SOLVE, s, 2 * sb, 0.0);
     line_solve(pl, op, spec_a, s);
   }
-  { Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, fft_flops(pl)); fft_time_inverse(pl, spec_a, out, out_f32, accumulate, variant, s); }
+  {
+    Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, time_flops(pl));
+    if (pl.hybrid) time_transform(pl, false, spec_a, out, out_f32, accumulate, s);
+    else fft_time_inverse(pl, spec_a, out, out_f32, accumulate, variant, s);
+  }
 }
 
 // y = b - A u (A u without b); with `sq`, also the partial sums of y . y, one
@@ -979,6 +1020,17 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
     }
     up(pl->d_lam, lam.data(), sizeof(double2) * 2 * g.F);
   }
+  if (pl->hybrid) {
+    const size_t fe = time_gemm_fragment_elems(g.nt);
+    pl->d_wf = (double*)take(sizeof(double) * fe);
+    pl->d_wi = (double*)take(sizeof(double) * fe);
+    pl->d_band = (double*)take(sizeof(double) * 5 * g.nt);
+    pl->d_band_t = (double*)take(sizeof(double) * 5 * g.nt);
+    up(pl->d_wf, pl->wf_frag.data(), sizeof(double) * fe);
+    up(pl->d_wi, pl->wi_frag.data(), sizeof(double) * fe);
+    up(pl->d_band, pl->band.data(), sizeof(double) * 5 * g.nt);
+    up(pl->d_band_t, pl->band_t.data(), sizeof(double) * 5 * g.nt);
+  }
   if (pl->p.dim == 2) {
     const int n = g.nx;
     for (int v = 0; v < 2; ++v) {
@@ -1090,7 +1142,7 @@ paradiag_status paradiag_build_rhs(paradiag_plan plan, const double* U0, const d
   Plan* pl = ready(plan);
   if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
   if (!U0 || !b) { set_error("U0 and b are required"); return PD_ERR_INVALID; }
-  build_rhs(*pl, U0, pl->p.scheme == PD_LEAPFROG ? u1 : nullptr, f, b, (hipStream_t)stream);
+  build_rhs(*pl, U0, (pl->p.scheme == PD_LEAPFROG || pl->p.scheme == PD_HYBRID_WAVE) ? u1 : nullptr, f, b, (hipStream_t)stream);
   return check_hip("build_rhs");
 }
 
@@ -1099,6 +1151,7 @@ paradiag_status paradiag_rhs_transpose(paradiag_plan plan, const double* lam, do
   Plan* pl = ready(plan);
   if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
   if (!lam || !gU0) { set_error("lam and gU0 are required"); return PD_ERR_INVALID; }
+  if (pl->hybrid) { set_error("rhs_transpose is not provided for the hybrid schemes"); return PD_ERR_UNSUPPORTED; }
   rhs_transpose(*pl, lam, gU0, gu1, gf, (hipStream_t)stream);
   return check_hip("rhs_transpose");
 }
@@ -1136,6 +1189,10 @@ static paradiag_status solve_entry(paradiag_plan plan, int variant, const double
     set_error("restart must be in [1, 32]"); return PD_ERR_INVALID;
   }
   if (opts->max_iter < 1 || !(opts->rtol > 0)) { set_error("max_iter >= 1 and rtol > 0 required"); return PD_ERR_INVALID; }
+  if (pl->hybrid && (variant != 0 || opts->mode == PD_MODE_FGMRES)) {
+    set_error("hybrid schemes (ParaDiag-I) solve in the direct and stationary modes only");
+    return PD_ERR_UNSUPPORTED;
+  }
   size_t nb = sizeof(double) * (size_t)pl->g.NA;
   if (overlap(b, nb, u, nb)) { set_error("b and u overlap"); return PD_ERR_INVALID; }
   try {

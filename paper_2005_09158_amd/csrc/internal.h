@@ -36,6 +36,20 @@ using cd = std::complex<double>;
 
 bool complex_schur(int n, std::vector<cd>& h, std::vector<cd>& q);
 
+// Eigendecomposition of the hybrid time matrix B (or B^2 for order 2) on the
+// half set of eigenvalues Re x > 0 (the others are their conjugates):
+//   d[n]            eigenvalue of B (order 1) or B^2 (order 2), n < nt/2
+//   wf[(2n+c)][l]   real (c = 0) and imaginary (c = 1) parts of V^{-1}[n][l]
+//   wi[l][(2n+c)]   2 Re V[l][n] (c = 0) and -2 Im V[l][n] (c = 1), so that
+//                   sum_c wi[l][2n+c] (S_n)_c = 2 Re(V[l][n] S_n)
+//   band[r][k+2]    entry (r, r+k) of B or B^2, |k| <= 2
+struct HybridTables {
+  std::vector<cd> d;
+  std::vector<double> wf, wi, band;
+  double inverse_error = 0.0;
+};
+bool hybrid_eigen(int nt, double dt, int order, HybridTables& out, std::string& err);
+
 // Workgroup order for the chip's 8 XCDs.  The dispatcher deals consecutive
 // workgroup ids round-robin to the XCDs, each with its own L2; renumbering
 // id -> (id mod 8) * share + id / 8 hands every XCD one contiguous range of
@@ -129,6 +143,16 @@ struct Plan {
   double2* d_tw64 = nullptr;
   float2* d_tw32 = nullptr;
   double2* d_lam = nullptr;        // [2][F]
+  // hybrid discretisation (ParaDiag-I): F = nt/2 eigenvalue pairs, time
+  // transforms by dense products (tables in MFMA fragment order), banded rows
+  // of the time matrix and of its transpose for the matvec
+  bool hybrid = false;
+  int order = 1;
+  std::vector<double> wf_frag, wi_frag, band, band_t;
+  double* d_wf = nullptr;
+  double* d_wi = nullptr;
+  double* d_band = nullptr;
+  double* d_band_t = nullptr;
   // spectral buffers
   void* spec_a = nullptr;
   void* spec_b = nullptr;
@@ -161,6 +185,12 @@ void fft_time_forward(const Plan& pl, const double* x, const double* bscale, int
 // Step-(c): z = Gamma^{-1} irfft_t(spec) (float64 or float32 output), optional accumulate.
 void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, int accumulate,
                       int reverse, hipStream_t s);
+// ParaDiag-I time transforms (hybrid discretisation): forward spec = V^{-1} x
+// (x float64 [B][nt][S]), inverse z (+)= V spec (z float64 or float32).
+void time_transform(const Plan& pl, bool forward, const void* in, void* out, bool out_f32,
+                    int accumulate, hipStream_t s);
+std::vector<double> time_gemm_fragments(const std::vector<double>& W, int nt);
+size_t time_gemm_fragment_elems(int nt);
 // Step-(b) pieces
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
            hipStream_t s);

@@ -235,6 +235,65 @@ __global__ __launch_bounds__(NT) void k_matvec(const Tin* __restrict__ u, const 
   }
 }
 
+// Matvec of the hybrid discretisation (Section 2.1.2): y_n = sum_{|k|<=2}
+// band[n][k+2] u_{n+k} + K u_n, the time matrix B (neq2.9c) or B^2 (neq2.15)
+// given by its banded rows (or those of its transpose), K by its 5-point
+// stencil.  Same grid and partial-sum layout as k_matvec with no Krylov dots:
+// y = b - A u when b is given, y not stored when null, and the partial sums
+// of y . y in slot 0 when sq.
+template <typename Tin, int V>
+__global__ __launch_bounds__(NT) void k_matvec_band(const Tin* __restrict__ u, const double* __restrict__ b,
+                                                    double* __restrict__ yv, int Nt, int nx, int ny,
+                                                    const double* __restrict__ band, Stencil st, int chunk,
+                                                    int sq, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int S = nx * ny;
+  const BlockPos bp = xcd_block();
+  const int s = (bp.x * NT + threadIdx.x) * V;
+  double asq = 0.0;
+  if (s < S) {
+    const int x = s % nx, y = s / nx;
+    const int64_t boff = (int64_t)bp.z * Nt * S;
+    const Tin* ub = u + boff;
+    const int nbeg = bp.y * chunk, nend = min(Nt, nbeg + chunk);
+    for (int n = nbeg; n < nend; ++n) {
+      double uu[V], ku[V], r[V];
+      points_and_k<Tin, V>(ub + (int64_t)n * S, x, y, nx, ny, st, uu, ku);
+      const double* bn = band + (int64_t)n * 5;
+#pragma unroll
+      for (int v = 0; v < V; ++v) r[v] = ku[v] + bn[2] * uu[v];
+#pragma unroll
+      for (int k = -2; k <= 2; ++k) {
+        if (k == 0 || n + k < 0 || n + k >= Nt || bn[k + 2] == 0.0) continue;
+        double w[V];
+        ldv<Tin, V>(ub + (int64_t)(n + k) * S + s, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) r[v] += bn[k + 2] * w[v];
+      }
+      const int64_t off = boff + (int64_t)n * S + s;
+      if (b) {
+        double bv[V];
+        ldv<double, V>(b + off, bv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) r[v] = bv[v] - r[v];
+      }
+      if (yv) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) yv[off + v] = r[v];
+      }
+      if (sq)
+#pragma unroll
+        for (int v = 0; v < V; ++v) asq += r[v] * r[v];
+    }
+  }
+  if (partial != nullptr && sq) {
+    const int chunks = gridDim.x * gridDim.y;
+    double* out = partial + ((int64_t)bp.z * chunks + bp.x + (int64_t)gridDim.x * bp.y) * MAXV;
+    const double t = block_sum(asq, red);
+    if (threadIdx.x == 0) out[0] = t;
+  }
+}
+
 // b from U0, u1, f (see paradiag_build_rhs); one thread per (n, point).
 __global__ __launch_bounds__(NT) void k_rhs(const double* __restrict__ U0, const double* __restrict__ V1,
                                             const double* __restrict__ f, double* __restrict__ b,
@@ -250,7 +309,17 @@ __global__ __launch_bounds__(NT) void k_rhs(const double* __restrict__ U0, const
   const double* fb = f ? f + (int64_t)bi * (Nt + 1) * S : nullptr;
   double r = 0.0;
   double uu, ku;
-  if (scheme != PD_LEAPFROG) {
+  if (scheme == PD_HYBRID || scheme == PD_HYBRID_WAVE) {
+    // rows n = 1 .. Nt carry f(t_n); the first-order form adds U0/(2 dt) to
+    // row 1, the second-order form u1/(2 dt) to row 1 and -U0/(4 dt^2) to row 2
+    if (fb) r = fb[(int64_t)(n + 1) * S + s];
+    if (scheme == PD_HYBRID) {
+      if (n == 0) r += u0b[s] / (2.0 * dt);
+    } else {
+      if (n == 0 && V1) r += V1[(int64_t)bi * S + s] / (2.0 * dt);
+      if (n == 1) r -= u0b[s] / (4.0 * dt * dt);
+    }
+  } else if (scheme != PD_LEAPFROG) {
     if (n == 0) {
       point_and_k(u0b, x, y, nx, ny, st, uu, ku);
       r = uu / dt - (1.0 - theta) * ku;
@@ -602,6 +671,15 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
   Stencil st = stencil_of(op);
   int dir = transpose ? -1 : 1;
   const Geom& g = pl.g;
+  if (pl.hybrid) {   // banded time matrix; Krylov dots are not fused here
+    const double* band = transpose ? pl.d_band_t : pl.d_band;
+#define PD_MVB(TIN, VV) \
+    k_matvec_band<TIN, VV><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, band, st, chunk, sq, partial)
+    if (u_is_f32) { if (V == 4) PD_MVB(float, 4); else PD_MVB(float, 1); }
+    else { if (V == 4) PD_MVB(double, 4); else PD_MVB(double, 1); }
+#undef PD_MVB
+    return;
+  }
 #define PD_MV(TIN, VV, K)                                                                         \
   k_matvec<TIN, VV, K><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0], \
                                            pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \

@@ -29,7 +29,7 @@ def make(params: dict, prec: str = "fp64", batch: int = 1, mode: str = "fgmres",
     from paper_2005_09158_amd import ParaDiag
     pd = ParaDiag(dim=params["dim"], nx=params["nx"], ny=params["ny"], nt=params["nt"],
                   scheme=params["scheme"], T=params["T"], nu=params["nu"], ax=params.get("ax", 0.0),
-                  ay=params.get("ay", 0.0), alpha=params["alpha"], batch=batch, prec=prec,
+                  ay=params.get("ay", 0.0), alpha=params.get("alpha", 1.0), batch=batch, prec=prec,
                   mode=mode, restart=restart)
     prob = Problem.from_kwargs(**params)
     return torch, pd, prob

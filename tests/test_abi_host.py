@@ -160,3 +160,39 @@ def test_xbasis_rejected_in_1d():
     q = (ctypes.c_double * 4)()
     assert lib.paradiag_get_xbasis(h, 0, q, q) == pd_lib.PD_ERR_INVALID
     lib.paradiag_destroy(h)
+
+
+@pytest.mark.parametrize("scheme,s,nt", [(3, "hyb", 64), (4, "hyb2", 24), (3, "hyb", 1024), (4, "hyb2", 2048)])
+def test_hybrid_eigenvalues_match_oracle(scheme, s, nt):
+    """The setup's closed-form eigenvalues of B (or B^2) for the hybrid scheme
+    (Thm thmCondU; the half set Im(lambda) > 0) against numpy's eigenvalues of
+    the oracle's assembled B (Nt <= 1024), or against the oracle's Newton roots."""
+    from oracle import hybrid
+    lib, st, h = _setup(scheme=scheme, nt=nt, ax=0.0, ay=0.0, T=2.0)
+    assert st == 0, lib.paradiag_last_error()
+    F = nt // 2
+    l1 = (ctypes.c_double * (2 * F))()
+    l2 = (ctypes.c_double * (2 * F))()
+    assert lib.paradiag_get_symbols(h, l1, l2) == 0
+    got = np.array(l1[:]).view(np.complex128)
+    assert np.allclose(np.array(l2[:]).view(np.complex128), 1.0)
+    dt = 2.0 / nt
+    lam = np.linalg.eigvals(hybrid.time_matrix(nt, dt))
+    lam = lam[lam.imag > 0]
+    want = lam if scheme == 3 else lam ** 2
+    assert got.size == want.size == F
+    d = np.abs(got[:, None] - want[None, :]).min(axis=1)
+    assert d.max() <= 1e-9 * np.abs(want).max()
+    # every eigenvalue is found once
+    assert np.unique(np.argmin(np.abs(got[:, None] - want[None, :]), axis=1)).size == F
+    lib.paradiag_destroy(h)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(scheme=3, nt=25), pd_lib.PD_ERR_UNSUPPORTED),   # odd nt
+    (dict(scheme=4, nt=2), pd_lib.PD_ERR_UNSUPPORTED),
+    (dict(scheme=3, nt=8192), pd_lib.PD_ERR_UNSUPPORTED),
+])
+def test_hybrid_setup_rejects(kw, code):
+    lib, st, h = _setup(**kw)
+    assert st == code
