@@ -27,4 +27,4 @@ Parity status of every function is stated in its module docstring.
 """
 
 from .problem import Problem  # noqa: F401
-from . import operators, rhs, solve, precond, krylov, adjoint, hybrid, parareal  # noqa: F401
+from . import operators, rhs, solve, precond, krylov, adjoint, hybrid, parareal, nonlinear  # noqa: F401
