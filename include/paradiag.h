@@ -102,7 +102,9 @@ typedef enum {
 typedef enum {
   PD_MODE_FGMRES = 0,      /* flexible GMRES(restart) preconditioned by P_alpha */
   PD_MODE_STATIONARY = 1,  /* u <- u + P_alpha^{-1}(b - A u)  (eq5.1) */
-  PD_MODE_DIRECT = 2       /* u = P_alpha^{-1} b once (solution of the alpha-circulant system) */
+  PD_MODE_DIRECT = 2,      /* u = P_alpha^{-1} b once (solution of the alpha-circulant system) */
+  PD_MODE_PARAREAL = 3,    /* workspace sizing of paradiag_parareal (not a paradiag_solve mode) */
+  PD_MODE_NONLINEAR = 4    /* workspace sizing of paradiag_nonlinear_solve (not a paradiag_solve mode) */
 } paradiag_mode;
 
 typedef struct {
@@ -211,6 +213,56 @@ paradiag_status paradiag_apply_precond_static(paradiag_plan plan, const double* 
 paradiag_status paradiag_solve(paradiag_plan plan, const double* b, double* u,
                                const paradiag_solve_opts* opts, paradiag_solve_info* info,
                                void* stream);
+
+/* ParaDiag-II parareal variant (Section 2.2.2, eq2.15): parareal for
+ * u' + K u = 0, u(0) = U0, on the plan's coarse grid of nt intervals of
+ * dT = T / nt, with the fine propagator F = J backward Euler steps of dT / J
+ * and the coarse-grid correction applied to the alpha-periodic problem
+ * u(0) = alpha u(T) (Thm the1.3: the same contraction as classical parareal
+ * for alpha below about 0.3).  Iteration k: Ut_n = F(U^{k-1}_{n-1}) for all n at
+ * once (U^{k-1}_0 = U0), then
+ *   (C1^(alpha) (x) I + I (x) K) u^k = b^k,
+ *   b^k_n = (I/dT + K) Ut_n - (n == 1 ? alpha U^{k-1}_nt : U^{k-1}_{n-1}) / dT,
+ * whose matrix is P_alpha of backward Euler, solved by the three steps of
+ * eq2.12.  The plan must use PD_BE in one space dimension (others:
+ * PD_ERR_UNSUPPORTED) and be bound with a workspace sized for
+ * PD_MODE_PARAREAL; opts->mode must be PD_MODE_PARAREAL.
+ * U0: [batch][nx] device float64.  u: [batch][nt][nx]; in = the initial
+ * iterate when opts->use_x0 (else zero), out = the last iterate, approximating
+ * the fine solution at t_1 .. t_nt.  Iterates until the relative change
+ * ||u^k - u^{k-1}||_2 / ||u^k||_2 <= opts->rtol for every right-hand side or
+ * opts->max_iter iterations (PD_NOT_CONVERGED); info->rel_resid and
+ * info->history report that relative change.  J in [1, 65536]. */
+paradiag_status paradiag_parareal(paradiag_plan plan, const double* U0, int32_t J, double* u,
+                                  const paradiag_solve_opts* opts, paradiag_solve_info* info,
+                                  void* stream);
+
+/* Pointwise cubic reaction g(u) = k1 u + k2 u^2 + k3 u^3 of paradiag_nonlinear_solve
+ * (Allen-Cahn: k1 = -1/eps^2, k2 = 0, k3 = 1/eps^2). */
+typedef struct { double k1, k2, k3; } paradiag_cubic;
+
+/* Nonlinear ParaDiag (eq1.4, eq1.5) with windowing: u' + K u + g(u) = 0,
+ * u(0) = U0, theta-method (PD_BE or PD_TR), so the all-at-once system of one
+ * window is (B1 (x) I) u + (B2 (x) I) F(u) = b with F(U) = K U + g(U) and
+ * b_1 = U0/dt - (1-theta) F(U0).  Each window runs the simplified Newton
+ * iteration u <- u + P_alpha(u)^{-1} R(u), R(u) = b - (B1 (x) I) u - (B2 (x) I) F(u),
+ * P_alpha(u) = C1^(alpha) (x) I + C2^(alpha) (x) (K + cbar I), where cbar is the
+ * mean of g'(U_n) over every time step and grid point (the averaged Jacobian,
+ * averaged over space too so that Step-(b) stays a shifted solve: lambda1_n
+ * becomes lambda1_n + cbar lambda2_n), starting from U_n = U0 for every n.  It
+ * stops when ||R(u)||_2 <= opts->rtol ||b||_2 or after opts->max_iter
+ * corrections.  Window w starts from the last state of window w-1 (windowing
+ * as at the end of Section 1).  batch must be 1; opts->mode must be
+ * PD_MODE_NONLINEAR (workspace sizing); opts->use_x0: window 0 starts from u
+ * instead of U0.  U0: [1][ny][nx]; u: [windows][1][nt][ny][nx].  info->iters =
+ * corrections over all windows, info->rel_resid = the largest final relative
+ * residual, info->history = the relative residual before every correction and
+ * at the end of each window.  The plan's time symbols (and line factors) are
+ * restored before returning.  Returns PD_NOT_CONVERGED when a window misses
+ * rtol (later windows still run). */
+paradiag_status paradiag_nonlinear_solve(paradiag_plan plan, const paradiag_cubic* g, const double* U0,
+                                         int32_t windows, double* u, const paradiag_solve_opts* opts,
+                                         paradiag_solve_info* info, void* stream);
 
 /* Solve A^T lam = g.  Uses A^T = (J (x) I)(B1 (x) I + B2 (x) K^T)(J (x) I) with J
  * the time reversal (Toeplitz and alpha-circulant matrices are persymmetric),

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "PD_OK", 1: "PD_NOT_CONVERGED", -1: "PD_ERR_INVALID", -2: "PD
 
 SCHEMES = {"be": 0, "tr": 1, "lf": 2, "hyb": 3, "hyb2": 4}
 PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2, "fp32_bf16x1": 3}
-MODES = {"fgmres": 0, "stationary": 1, "direct": 2}
+MODES = {"fgmres": 0, "stationary": 1, "direct": 2, "parareal": 3, "nonlinear": 4}
 STAGES = ["fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv", "matvec", "dot", "update",
           "other"]
 
@@ -40,6 +40,10 @@ class Problem(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("use_x0", ctypes.c_int32), ("rtol", ctypes.c_double)]
+
+
+class Cubic(ctypes.Structure):
+    _fields_ = [("k1", ctypes.c_double), ("k2", ctypes.c_double), ("k3", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -65,6 +69,10 @@ SIGNATURES = {
     "paradiag_apply_precond_static": (ctypes.c_int, [_P, _P, _P, _P]),
     "paradiag_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "paradiag_adjoint_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
+    "paradiag_parareal": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.POINTER(SolveOpts),
+                                         ctypes.POINTER(SolveInfo), _P]),
+    "paradiag_nonlinear_solve": (ctypes.c_int, [_P, ctypes.POINTER(Cubic), _P, ctypes.c_int32, _P,
+                                                ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _P]),
     "paradiag_get_xbasis": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D]),
     "paradiag_get_symbols": (ctypes.c_int, [_P, _D, _D]),
     "paradiag_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),

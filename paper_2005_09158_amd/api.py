@@ -174,6 +174,57 @@ class ParaDiag:
         return self._solve(self.lib.paradiag_adjoint_solve, "paradiag_adjoint_solve", g, lam, mode,
                            rtol, max_iter, restart, x0)
 
+    def parareal(self, U0: torch.Tensor, J: int, u: Optional[torch.Tensor] = None, *,
+                 rtol: float = 1e-10, max_iter: int = 50, x0: Optional[torch.Tensor] = None):
+        """paradiag_parareal: the ParaDiag-II parareal variant from U0 ([batch, 1, nx]),
+        J fine backward Euler steps per coarse interval; returns (u, SolveResult)
+        with u [batch, nt, 1, nx] and rel_resid the last relative change."""
+        if u is None:
+            u = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        if x0 is not None:
+            u.copy_(x0)
+        opts = _lib.SolveOpts(mode=_lib.MODES["parareal"], restart=1, max_iter=max_iter,
+                              use_x0=int(x0 is not None), rtol=rtol)
+        it = (ctypes.c_int32 * self.batch)()
+        rs = (ctypes.c_double * self.batch)()
+        cap = max_iter + 4
+        hist = (ctypes.c_double * cap)()
+        info = _lib.SolveInfo(iters=0, converged=0, rel_resid=0.0, iters_per_rhs=it,
+                              resid_per_rhs=rs, history=hist, history_cap=cap, history_len=0)
+        st = self.lib.paradiag_parareal(self.plan, _ptr(U0, self.field_shape, "U0"), int(J),
+                                        _ptr(u, self.shape, "u"), ctypes.byref(opts), ctypes.byref(info),
+                                        _stream())
+        _lib.check(st, "paradiag_parareal", allow_not_converged=True)
+        return u, SolveResult(st, info.iters, bool(info.converged), info.rel_resid, list(it), list(rs),
+                              list(hist[: info.history_len]))
+
+    def nonlinear_solve(self, U0: torch.Tensor, k1: float = 0.0, k2: float = 0.0, k3: float = 0.0, *,
+                        windows: int = 1, u: Optional[torch.Tensor] = None, rtol: float = 1e-10,
+                        max_iter: int = 50, x0: Optional[torch.Tensor] = None):
+        """paradiag_nonlinear_solve: u' + K u + g(u) = 0 with g(u) = k1 u + k2 u^2 + k3 u^3,
+        simplified Newton with the averaged Jacobian over `windows` consecutive
+        windows; returns (u [windows, 1, nt, ny, nx], SolveResult)."""
+        shape = (windows,) + self.shape
+        if u is None:
+            u = torch.empty(shape, dtype=torch.float64, device=self.device)
+        if x0 is not None:
+            u[0].copy_(x0)
+        opts = _lib.SolveOpts(mode=_lib.MODES["nonlinear"], restart=1, max_iter=max_iter,
+                              use_x0=int(x0 is not None), rtol=rtol)
+        it = (ctypes.c_int32 * self.batch)()
+        rs = (ctypes.c_double * self.batch)()
+        cap = windows * (max_iter + 2) + 4
+        hist = (ctypes.c_double * cap)()
+        info = _lib.SolveInfo(iters=0, converged=0, rel_resid=0.0, iters_per_rhs=it,
+                              resid_per_rhs=rs, history=hist, history_cap=cap, history_len=0)
+        gc = _lib.Cubic(k1=k1, k2=k2, k3=k3)
+        st = self.lib.paradiag_nonlinear_solve(self.plan, ctypes.byref(gc), _ptr(U0, self.field_shape, "U0"),
+                                               int(windows), _ptr(u, shape, "u"), ctypes.byref(opts),
+                                               ctypes.byref(info), _stream())
+        _lib.check(st, "paradiag_nonlinear_solve", allow_not_converged=True)
+        return u, SolveResult(st, info.iters, bool(info.converged), info.rel_resid, list(it), list(rs),
+                              list(hist[: info.history_len]))
+
     # ----------------------------------------------------------- inspection
     def set_timing(self, enable, stages=None) -> None:
         """Turn stage timing on or off; with `stages` (names as in stage_times),

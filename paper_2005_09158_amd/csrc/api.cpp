@@ -270,6 +270,11 @@ size_t solver_bytes(const Plan& pl, const paradiag_solve_opts* o) {
   }
   // stationary: the residual vector; direct: only the norm of its residual
   if (o->mode == PD_MODE_DIRECT) return small;
+  // parareal: the previous iterate and the coarse right-hand side
+  if (o->mode == PD_MODE_PARAREAL) return small + 2 * align_up(sizeof(double) * (size_t)g.NA);
+  // nonlinear: residual, right-hand side, the next window's initial state
+  if (o->mode == PD_MODE_NONLINEAR)
+    return small + 2 * align_up(sizeof(double) * (size_t)g.NA) + align_up(sizeof(double) * (size_t)g.B * g.S);
   return small + align_up(sizeof(double) * (size_t)g.NA);
 }
 
@@ -965,7 +970,7 @@ paradiag_status paradiag_workspace_size(paradiag_plan plan, const paradiag_solve
                                         size_t* bytes) {
   Plan* pl = reinterpret_cast<Plan*>(plan);
   if (!pl || !bytes) { set_error("NULL argument"); return PD_ERR_INVALID; }
-  if (opts && (opts->mode < 0 || opts->mode > 2)) { set_error("unknown mode"); return PD_ERR_INVALID; }
+  if (opts && (opts->mode < 0 || opts->mode > 4)) { set_error("unknown mode"); return PD_ERR_INVALID; }
   *bytes = tables_bytes(*pl) + solver_bytes(*pl, opts);
   return PD_OK;
 }
@@ -1184,7 +1189,7 @@ static paradiag_status solve_entry(paradiag_plan plan, int variant, const double
   Plan* pl = ready(plan);
   if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
   if (!b || !u || !opts) { set_error("NULL argument"); return PD_ERR_INVALID; }
-  if (opts->mode < 0 || opts->mode > 2) { set_error("unknown mode"); return PD_ERR_INVALID; }
+  if (opts->mode < 0 || opts->mode > 2) { set_error("unknown mode (parareal has its own entry point)"); return PD_ERR_INVALID; }
   if (opts->mode == PD_MODE_FGMRES && (opts->restart < 1 || opts->restart > 32)) {
     set_error("restart must be in [1, 32]"); return PD_ERR_INVALID;
   }
@@ -1201,6 +1206,182 @@ static paradiag_status solve_entry(paradiag_plan plan, int variant, const double
     set_error("solve failed (host allocation)");
     return PD_ERR_INVALID;
   }
+}
+
+paradiag_status paradiag_parareal(paradiag_plan plan, const double* U0, int32_t J, double* u,
+                                  const paradiag_solve_opts* o, paradiag_solve_info* info,
+                                  void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!U0 || !u || !o) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (o->mode != PD_MODE_PARAREAL) { set_error("opts->mode must be PD_MODE_PARAREAL"); return PD_ERR_INVALID; }
+  if (J < 1 || J > 65536) { set_error("J must lie in [1, 65536]"); return PD_ERR_INVALID; }
+  if (o->max_iter < 1 || !(o->rtol > 0)) { set_error("max_iter >= 1 and rtol > 0 required"); return PD_ERR_INVALID; }
+  if (pl->p.scheme != PD_BE || pl->p.dim != 1) {
+    set_error("parareal needs a backward Euler plan in one space dimension");
+    return PD_ERR_UNSUPPORTED;
+  }
+  const Geom& g = pl->g;
+  const size_t nb = sizeof(double) * (size_t)g.NA;
+  if (overlap(U0, sizeof(double) * (size_t)g.B * g.S, u, nb)) { set_error("U0 and u overlap"); return PD_ERR_INVALID; }
+  if ((size_t)(pl->ws + pl->ws_bytes - pl->solver_base) < solver_bytes(*pl, o)) {
+    set_error("workspace too small for parareal (see paradiag_workspace_size with PD_MODE_PARAREAL)");
+    return PD_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* p = pl->solver_base;
+  Small sm = carve_small(*pl, p);
+  double* uprev = (double*)p;
+  p += align_up(nb);
+  double* bvec = (double*)p;
+  if (!pinned(*pl)) { set_error("pinned host staging allocation failed"); return PD_ERR_HIP; }
+  if (!o->use_x0) fill_zero(u, g.NA, s);
+  const int chunks = std::max(1, std::min(512, (int)(g.N1 / (256 * 16))));
+  std::vector<double> rel(g.B, 0.0);
+  int iters = 0, hist = 0;
+  bool conv = false;
+  while (iters < o->max_iter) {
+    copy_vec(u, uprev, g.NA, s);
+    parareal_fine(*pl, U0, uprev, bvec, J, pl->p.alpha, s);
+    apply_prec(*pl, 0, bvec, nullptr, 0, u, false, 0, s);
+    diff_norms(*pl, u, uprev, sm.partial, chunks, s);
+    timed_reduce(*pl, sm.partial, 2, nullptr, 0, sm.nrm, nullptr, s, chunks, pl->pin);
+    if (paradiag_status st = wait_host(*pl, s); st != PD_OK) return st;
+    ++iters;
+    double mx = 0.0;
+    for (int b = 0; b < g.B; ++b) {
+      const double dd = pl->pin[(size_t)b * MAXV], uu = pl->pin[(size_t)b * MAXV + 1];
+      rel[b] = uu > 0 ? std::sqrt(dd / uu) : (dd > 0 ? INFINITY : 0.0);
+      if (!std::isfinite(rel[b])) { set_error("non-finite parareal iterate"); return PD_ERR_NONFINITE; }
+      mx = std::max(mx, rel[b]);
+    }
+    if (info && info->history && hist < info->history_cap) info->history[hist] = mx;
+    ++hist;
+    if (mx <= o->rtol) { conv = true; break; }
+  }
+  if (info) {
+    double mx = 0.0;
+    for (int b = 0; b < g.B; ++b) {
+      mx = std::max(mx, rel[b]);
+      if (info->iters_per_rhs) info->iters_per_rhs[b] = iters;
+      if (info->resid_per_rhs) info->resid_per_rhs[b] = rel[b];
+    }
+    info->iters = iters;
+    info->converged = conv ? 1 : 0;
+    info->rel_resid = mx;
+    info->history_len = std::min(hist, info->history ? info->history_cap : 0);
+  }
+  if (paradiag_status st = check_hip("parareal"); st != PD_OK) return st;
+  return conv ? PD_OK : PD_NOT_CONVERGED;
+}
+
+// Uploads lambda1_n + shift lambda2_n (and lambda2) to the device table and
+// refactors the back-sweep's lines; shift 0 restores the plan's own symbols.
+static void shift_symbols(Plan& pl, double shift, bool both_ops, hipStream_t s) {
+  const int F = pl.g.F;
+  pl.lam_stage.resize(2 * (size_t)F);
+  for (int n = 0; n < F; ++n) {
+    const cd l1 = pl.lam1[n] + shift * pl.lam2[n];
+    pl.lam_stage[n] = double2{l1.real(), l1.imag()};
+    pl.lam_stage[F + n] = double2{pl.lam2[n].real(), pl.lam2[n].imag()};
+  }
+  hipMemcpyAsync(pl.d_lam, pl.lam_stage.data(), sizeof(double2) * 2 * F, hipMemcpyHostToDevice, s);
+  if (pl.p.dim == 2 && pl.schur) {
+    schur_line_lu(pl, pl.op[0], s);
+    if (both_ops) schur_line_lu(pl, pl.op[1], s);
+  }
+}
+
+paradiag_status paradiag_nonlinear_solve(paradiag_plan plan, const paradiag_cubic* gc, const double* U0,
+                                         int32_t windows, double* u, const paradiag_solve_opts* o,
+                                         paradiag_solve_info* info, void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!gc || !U0 || !u || !o) { set_error("NULL argument"); return PD_ERR_INVALID; }
+  if (o->mode != PD_MODE_NONLINEAR) { set_error("opts->mode must be PD_MODE_NONLINEAR"); return PD_ERR_INVALID; }
+  if (windows < 1 || o->max_iter < 1 || !(o->rtol > 0)) {
+    set_error("windows >= 1, max_iter >= 1 and rtol > 0 required"); return PD_ERR_INVALID;
+  }
+  if (!std::isfinite(gc->k1) || !std::isfinite(gc->k2) || !std::isfinite(gc->k3)) {
+    set_error("non-finite reaction coefficients"); return PD_ERR_INVALID;
+  }
+  if (pl->hybrid || (pl->p.scheme != PD_BE && pl->p.scheme != PD_TR) || pl->g.B != 1) {
+    set_error("nonlinear solves need a theta-method plan (PD_BE, PD_TR) with batch 1");
+    return PD_ERR_UNSUPPORTED;
+  }
+  const Geom& g = pl->g;
+  const size_t nb = sizeof(double) * (size_t)g.NA;
+  if (overlap(U0, sizeof(double) * (size_t)g.S, u, nb * (size_t)windows)) { set_error("U0 and u overlap"); return PD_ERR_INVALID; }
+  if ((size_t)(pl->ws + pl->ws_bytes - pl->solver_base) < solver_bytes(*pl, o)) {
+    set_error("workspace too small for the nonlinear solver (see paradiag_workspace_size with PD_MODE_NONLINEAR)");
+    return PD_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* p = pl->solver_base;
+  Small sm = carve_small(*pl, p);
+  double* r = (double*)p;
+  p += align_up(nb);
+  double* bvec = (double*)p;
+  p += align_up(nb);
+  double* u0buf = (double*)p;
+  if (!pinned(*pl)) { set_error("pinned host staging allocation failed"); return PD_ERR_HIP; }
+  const double gk[3] = {gc->k1, gc->k2, gc->k3};
+  const int chunks = std::max(1, std::min(512, (int)(g.N1 / (256 * 16))));
+  int iters = 0, hist = 0;
+  bool all_conv = true;
+  double worst = 0.0;
+  auto record = [&](double v) {
+    if (info && info->history && hist < info->history_cap) info->history[hist] = v;
+    ++hist;
+  };
+  paradiag_status st = PD_OK;
+  for (int w = 0; w < windows && st == PD_OK; ++w) {
+    double* uw = u + (size_t)w * g.NA;
+    const double* U0w = U0;
+    if (w > 0) {
+      last_rows(*pl, uw - g.NA, u0buf, s);
+      U0w = u0buf;
+    }
+    build_rhs(*pl, U0w, nullptr, nullptr, bvec, s);
+    nl_rhs_fix(*pl, U0w, bvec, gk, s);
+    std::vector<double> bn;
+    timed_dot(*pl, bvec, 0, 1, bvec, sm.partial, s);
+    if ((st = norms_from(*pl, sm, bn, s)) != PD_OK) break;
+    if (!(w == 0 && o->use_x0)) bcast_rows(*pl, U0w, uw, s);
+    double rel = 0.0;
+    bool conv = false;
+    for (int it = 0;; ++it) {
+      apply_A(*pl, 0, uw, false, bvec, r, s);          // r = b - (B1 (x) I + B2 (x) K) u
+      nl_residual(*pl, uw, r, gk, sm.partial, chunks, s);
+      timed_reduce(*pl, sm.partial, 2, nullptr, 0, sm.nrm, nullptr, s, chunks, pl->pin);
+      if ((st = wait_host(*pl, s)) != PD_OK) break;
+      const double rr = pl->pin[0], gsum = pl->pin[1];
+      rel = bn[0] > 0 ? std::sqrt(std::fabs(rr)) / bn[0] : std::sqrt(std::fabs(rr));
+      if (!std::isfinite(rel) || !std::isfinite(gsum)) { set_error("non-finite nonlinear residual"); st = PD_ERR_NONFINITE; break; }
+      record(rel);
+      if (rel <= o->rtol) { conv = true; break; }
+      if (it >= o->max_iter) break;
+      shift_symbols(*pl, gsum / (double)g.NA, false, s);   // P_alpha(u) with the averaged slope
+      apply_prec(*pl, 0, r, nullptr, 0, uw, false, 1, s);  // u += P_alpha(u)^{-1} R(u)
+      ++iters;
+    }
+    worst = std::max(worst, rel);
+    all_conv = all_conv && conv;
+  }
+  shift_symbols(*pl, 0.0, true, s);   // the plan's own symbols and line factors again
+  if (st == PD_OK) st = check_hip("nonlinear solve");
+  if (info) {
+    info->iters = iters;
+    info->converged = all_conv && st == PD_OK ? 1 : 0;
+    info->rel_resid = worst;
+    info->history_len = std::min(hist, info->history ? info->history_cap : 0);
+    if (info->iters_per_rhs) info->iters_per_rhs[0] = iters;
+    if (info->resid_per_rhs) info->resid_per_rhs[0] = worst;
+  }
+  if (st != PD_OK) return st;
+  hipError_t e = hipStreamSynchronize(s);   // the restored symbols are in place on return
+  if (e != hipSuccess) { set_error(std::string("nonlinear solve: ") + hipGetErrorString(e)); return PD_ERR_HIP; }
+  return all_conv ? PD_OK : PD_NOT_CONVERGED;
 }
 
 paradiag_status paradiag_solve(paradiag_plan plan, const double* b, double* u,

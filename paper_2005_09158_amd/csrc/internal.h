@@ -149,6 +149,9 @@ struct Plan {
   bool hybrid = false;
   int order = 1;
   std::vector<double> wf_frag, wi_frag, band, band_t;
+  // host staging of the shifted time symbols of the nonlinear solver (kept
+  // alive until the plan is destroyed: an asynchronous copy reads it)
+  std::vector<double2> lam_stage;
   double* d_wf = nullptr;
   double* d_wi = nullptr;
   double* d_band = nullptr;
@@ -249,6 +252,21 @@ void arnoldi_skip(const Plan& pl, const double* h, const double* giv, int gs, in
 void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int nz,
               const double* y, double* x, bool overwrite, hipStream_t s);
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s);
+// partial[b][chunk][0..1] = sums of (u - v)^2 and u^2 over chunk `chunk` of right-hand side b
+void diff_norms(const Plan& pl, const double* u, const double* v, double* partial, int chunks,
+                hipStream_t s);
+// Nonlinear problems (eq1.4, g(u) = gk[0] u + gk[1] u^2 + gk[2] u^3): r -= (B2 (x) I) g(u) with
+// partial sums [b][chunk] of r^2 (slot 0) and g'(u) (slot 1); b_1 -= (1-theta) g(U0);
+// u_n = U0 for all n; dst[b] = src[b][nt-1].
+void nl_residual(const Plan& pl, const double* u, double* r, const double* gk, double* partial, int chunks,
+                 hipStream_t s);
+void nl_rhs_fix(const Plan& pl, const double* U0, double* b, const double* gk, hipStream_t s);
+void bcast_rows(const Plan& pl, const double* U0, double* u, hipStream_t s);
+void last_rows(const Plan& pl, const double* src, double* dst, hipStream_t s);
+// Parareal (1D): b = right-hand side of the alpha-periodic coarse-grid
+// correction after J fine backward Euler steps from U0 / the iterate uprev.
+void parareal_fine(const Plan& pl, const double* U0, const double* uprev, double* b, int J, double alpha,
+                   hipStream_t s);
 void fill_zero(double* dst, int64_t n, hipStream_t s);
 
 }  // namespace pd

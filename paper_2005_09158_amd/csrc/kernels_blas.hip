@@ -384,6 +384,85 @@ __global__ __launch_bounds__(NT) void k_rhs_t(const double* __restrict__ lam, do
 }
 
 
+// partial[b][chunk][0] = sum over the chunk of (u - v)^2, [1] = sum of u^2
+// (the relative change of a fixed-point iterate, e.g. parareal's)
+__global__ __launch_bounds__(NT) void k_diff_sq(const double* __restrict__ u, const double* __restrict__ v,
+                                                double* __restrict__ partial, int64_t N1, int chunks) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int64_t len = (N1 + chunks - 1) / chunks, beg = (int64_t)c * len, end = min(N1, beg + len);
+  const double* ub = u + (int64_t)b * N1;
+  const double* vb = v + (int64_t)b * N1;
+  double dd = 0.0, uu = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += NT) {
+    const double x = ub[i], y = x - vb[i];
+    dd += y * y;
+    uu += x * x;
+  }
+  double* out = partial + ((int64_t)b * chunks + c) * MAXV;
+  const double t0 = block_sum(dd, red);
+  if (threadIdx.x == 0) out[0] = t0;
+  const double t1 = block_sum(uu, red);
+  if (threadIdx.x == 0) out[1] = t1;
+}
+
+// Nonlinear problems U' + K U + g(U) = 0, g(u) = k1 u + k2 u^2 + k3 u^3
+// (eq1.4): the nonlinear part of the residual, r_n -= c2_0 g(U_n) + c2_1
+// g(U_{n-1}) (n >= 1; row 1's U_0 term sits in b), with partial sums of r^2
+// (slot 0) and of g'(U) (slot 1, for the averaged Jacobian) per chunk.
+struct CubicG {
+  double k1, k2, k3;
+  __device__ __forceinline__ double g(double u) const { return u * (k1 + u * (k2 + u * k3)); }
+  __device__ __forceinline__ double dg(double u) const { return k1 + u * (2.0 * k2 + 3.0 * k3 * u); }
+};
+
+__global__ __launch_bounds__(NT) void k_nl_residual(const double* __restrict__ u, double* __restrict__ r,
+                                                    int64_t N1, int S, double c20, double c21, CubicG gc,
+                                                    double* __restrict__ partial, int chunks) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int64_t len = (N1 + chunks - 1) / chunks, beg = (int64_t)c * len, end = min(N1, beg + len);
+  const double* ub = u + (int64_t)b * N1;
+  double* rb = r + (int64_t)b * N1;
+  double rr = 0.0, gs = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += NT) {
+    const double x = ub[i];
+    double v = rb[i] - c20 * gc.g(x);
+    if (c21 != 0.0 && i >= S) v -= c21 * gc.g(ub[i - S]);
+    rb[i] = v;
+    rr += v * v;
+    gs += gc.dg(x);
+  }
+  double* out = partial + ((int64_t)b * chunks + c) * MAXV;
+  const double t0 = block_sum(rr, red);
+  if (threadIdx.x == 0) out[0] = t0;
+  const double t1 = block_sum(gs, red);
+  if (threadIdx.x == 0) out[1] = t1;
+}
+
+// b_1 -= w g(U0) (the known initial state's share of row 1; w = 1 - theta)
+__global__ __launch_bounds__(NT) void k_nl_rhs_fix(const double* __restrict__ U0, double* __restrict__ b,
+                                                   int S, int64_t N1, double w, CubicG gc) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= S) return;
+  b[(int64_t)blockIdx.y * N1 + e] -= w * gc.g(U0[(int64_t)blockIdx.y * S + e]);
+}
+
+// u_n = U0 for every n (the starting iterate), and the gather of the last
+// time step of a block of rows: dst[b] = src[b][nt-1]
+__global__ __launch_bounds__(NT) void k_bcast_rows(const double* __restrict__ U0, double* __restrict__ u,
+                                                   int S, int nt) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)nt * S) return;
+  u[(int64_t)blockIdx.y * nt * S + e] = U0[(int64_t)blockIdx.y * S + e % S];
+}
+__global__ __launch_bounds__(NT) void k_last_rows(const double* __restrict__ src, double* __restrict__ dst,
+                                                  int S, int nt) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= S) return;
+  dst[(int64_t)blockIdx.y * S + e] = src[((int64_t)blockIdx.y * nt + nt - 1) * S + e];
+}
+
 // Multi-dot and update kernels, templated on the number of Krylov vectors
 // (NV <= 8; larger counts use the generic predicated form).  Each thread
 // handles pairs of consecutive doubles (16-byte loads); a workgroup owns one
@@ -799,6 +878,29 @@ void x_update(const Plan& pl, const void* Z, bool z_is_f32, int64_t zstride, int
     k_xupd<float><<<grid, NT, 0, s>>>((const float*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
   else
     k_xupd<double><<<grid, NT, 0, s>>>((const double*)Z, zstride, nz, y, MAXV, x, pl.g.N1, overwrite);
+}
+
+void diff_norms(const Plan& pl, const double* u, const double* v, double* partial, int chunks,
+                hipStream_t s) {
+  k_diff_sq<<<dim3(chunks, pl.g.B), NT, 0, s>>>(u, v, partial, pl.g.N1, chunks);
+}
+
+void nl_residual(const Plan& pl, const double* u, double* r, const double* gk, double* partial, int chunks,
+                 hipStream_t s) {
+  k_nl_residual<<<dim3(chunks, pl.g.B), NT, 0, s>>>(u, r, pl.g.N1, (int)pl.g.S, pl.c2[0], pl.c2[1],
+                                                    CubicG{gk[0], gk[1], gk[2]}, partial, chunks);
+}
+void nl_rhs_fix(const Plan& pl, const double* U0, double* b, const double* gk, hipStream_t s) {
+  const dim3 grid((unsigned)((pl.g.S + NT - 1) / NT), pl.g.B);
+  k_nl_rhs_fix<<<grid, NT, 0, s>>>(U0, b, (int)pl.g.S, pl.g.N1, 1.0 - pl.theta, CubicG{gk[0], gk[1], gk[2]});
+}
+void bcast_rows(const Plan& pl, const double* U0, double* u, hipStream_t s) {
+  const dim3 grid((unsigned)((pl.g.N1 + NT - 1) / NT), pl.g.B);
+  k_bcast_rows<<<grid, NT, 0, s>>>(U0, u, (int)pl.g.S, pl.g.nt);
+}
+void last_rows(const Plan& pl, const double* src, double* dst, hipStream_t s) {
+  const dim3 grid((unsigned)((pl.g.S + NT - 1) / NT), pl.g.B);
+  k_last_rows<<<grid, NT, 0, s>>>(src, dst, (int)pl.g.S, pl.g.nt);
 }
 
 void copy_vec(const double* src, double* dst, int64_t n, hipStream_t s) {
