@@ -237,6 +237,37 @@ paradiag_status paradiag_parareal(paradiag_plan plan, const double* U0, int32_t 
                                   const paradiag_solve_opts* opts, paradiag_solve_info* info,
                                   void* stream);
 
+/* Optimal control of the wave equation (Section 4).  Setup of the plan of
+ * the gamma-scaled optimality system
+ *   A x = b,  x = [sqrt(gamma) u; p],
+ *   A = [[B1, -s Ih], [s Ic, B1^T]] (x) I + (dt^2/2) blkdiag(B2, B2^T) (x) K,
+ * B1 = Toeplitz(1, -2, 1), B2 = Toeplitz(1, 0, 1) (implicit leap-frog, dt = T/nt),
+ * Ih = diag(1/2, 1, .., 1), Ic = diag(1, .., 1, 1/2), s = dt^2 / sqrt(gamma), K the
+ * spatial operator of `prob` (nu times the negative Laplacian; prob->scheme
+ * must be PD_LEAPFROG, ax = ay = 0, batch 1), u = u(t_1 .. t_nt) the state and
+ * p = p(t_0 .. t_{nt-1}) the adjoint.  The plan's vectors are [2][nt][ny][nx]
+ * (x1 = sqrt(gamma) u, then x2 = p).  Its preconditioner (apply_precond, and
+ * inside paradiag_solve) is the block circulant P of Section 4 (B1, B2 replaced
+ * by their circulants, Ih, Ic by I), applied as in Thm the4: DFTs of both
+ * fields along time (dense float64 products on MFMA: nt need not be a power
+ * of two), a 2 x 2 mixing per frequency with perfectly conditioned
+ * eigenvectors, 2 (nt/2 + 1) shifted solves (Sigma_n I + dt^2/2 K), the
+ * unmixing with C2^{-1}, and the inverse DFTs.  nt must not be divisible by 4
+ * (C2 is singular then), 3 <= nt <= 4096.  Supported afterwards:
+ * workspace_size, bind_workspace, matvec (not the transpose), apply_precond
+ * (and _static), solve in every mode, oc_build_rhs; build_rhs, rhs_transpose
+ * and adjoint_solve return PD_ERR_UNSUPPORTED. */
+paradiag_status paradiag_oc_setup(const paradiag_problem* prob, double gamma, paradiag_plan* out);
+
+/* b = [sqrt(gamma) fh; gh] of the optimal-control plan from the data of
+ * Section 4: fh = dt^2 times the implicit leap-frog rows of the state
+ * equation with u(0) = U0, u_t(0) = u1 (NULL = 0) and source f
+ * ([nt+1][ny][nx] at t_0..t_nt, NULL = 0), as paradiag_build_rhs builds them for
+ * PD_LEAPFROG; gh_m = dt^2 g(t_{m+1}) with the last row halved (g [nt+1][ny][nx],
+ * NULL = 0).  b: [2][nt][ny][nx]. */
+paradiag_status paradiag_oc_build_rhs(paradiag_plan plan, const double* U0, const double* u1,
+                                      const double* f, const double* g, double* b, void* stream);
+
 /* Pointwise cubic reaction g(u) = k1 u + k2 u^2 + k3 u^3 of paradiag_nonlinear_solve
  * (Allen-Cahn: k1 = -1/eps^2, k2 = 0, k3 = 1/eps^2). */
 typedef struct { double k1, k2, k3; } paradiag_cubic;

@@ -22,9 +22,13 @@ What it computes, all in float64, each function citing the passage it follows:
   eigendecomposition and exact all-at-once solves.
 * ``parareal``   classical parareal and the ParaDiag-II parareal variant with
   the alpha-periodic coarse-grid correction (Section 2.2.2).
+* ``nonlinear``  nonlinear ParaDiag with the averaged Jacobian (eq1.4, eq1.5)
+  and windowing.
+* ``ocwave``     the optimality system of the optimal control of the wave
+  equation and its block-circulant preconditioner (Section 4, Thm the4).
 
 Parity status of every function is stated in its module docstring.
 """
 
 from .problem import Problem  # noqa: F401
-from . import operators, rhs, solve, precond, krylov, adjoint, hybrid, parareal, nonlinear  # noqa: F401
+from . import operators, rhs, solve, precond, krylov, adjoint, hybrid, parareal, nonlinear, ocwave  # noqa: F401

@@ -60,6 +60,8 @@ _D = ctypes.POINTER(ctypes.c_double)
 # name -> (restype, argtypes); every symbol include/paradiag.h declares
 SIGNATURES = {
     "paradiag_setup": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(_P)]),
+    "paradiag_oc_setup": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_double, ctypes.POINTER(_P)]),
+    "paradiag_oc_build_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "paradiag_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)]),
     "paradiag_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "paradiag_build_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),

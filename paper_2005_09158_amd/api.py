@@ -295,3 +295,41 @@ class ParaDiagSolve(torch.autograd.Function):
             raise RuntimeError(f"adjoint solve did not converge: {res}")
         gU0, _gu1, gf = pd.rhs_transpose(lam)
         return None, gU0, gf, None
+
+
+class ParaDiagOC(ParaDiag):
+    """Plan of the optimal control of the wave equation (``paradiag_oc_setup``,
+    Section 4): vectors [2, nt, ny, nx] holding sqrt(gamma) u and p; matvec,
+    apply_precond and solve as for ParaDiag, plus ``build_rhs`` from (U0, u1, f, g)."""
+
+    def __init__(self, *, dim: int, nx: int, ny: int, nt: int, T: float, nu: float, gamma: float,
+                 prec: str = "fp64", mode: str = "fgmres", restart: int = 30,
+                 device: Optional[torch.device] = None):
+        self.lib = _lib.load()
+        self.shape = (2, nt, ny, nx)
+        self.field_shape = (1, ny, nx)
+        self.source_shape = (1, nt + 1, ny, nx)
+        self.batch, self.nt, self.ny, self.nx = 1, nt, ny, nx
+        self.gamma = gamma
+        self.prob = _lib.Problem(dim=dim, nx=nx, ny=ny, nt=nt, batch=1, scheme=_lib.SCHEMES["lf"],
+                                 prec=_lib.PRECS[prec], reserved=0, T=T, nu=nu, ax=0.0, ay=0.0, alpha=1.0)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.paradiag_oc_setup(ctypes.byref(self.prob), ctypes.c_double(gamma), ctypes.byref(h)),
+                   "paradiag_oc_setup")
+        self.plan = h
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self._ws = None
+        self.bind_workspace(mode, restart)
+
+    def build_rhs(self, U0: torch.Tensor, u1: Optional[torch.Tensor] = None,
+                  f: Optional[torch.Tensor] = None, g: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        b = out if out is not None else torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.paradiag_oc_build_rhs(self.plan, _ptr(U0, self.field_shape, "U0"),
+                                                  _ptr(u1, self.field_shape, "u1"),
+                                                  _ptr(f, self.source_shape, "f"),
+                                                  _ptr(g, self.source_shape, "g"),
+                                                  _ptr(b, self.shape, "b"), _stream()),
+                   "paradiag_oc_build_rhs")
+        return b
+

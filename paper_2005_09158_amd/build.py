@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libparadiag.so")
 
 SOURCES = ["api.cpp", "schur.cpp", "kernels_fft.hip", "kernels_tri.hip", "kernels_sweep.hip", "kernels_gemm.hip",
            "kernels_blas.hip", "static_scratch.hip", "hybrid.cpp",
-           "kernels_hybrid.hip", "kernels_parareal.hip"]
+           "kernels_hybrid.hip", "kernels_parareal.hip",
+           "kernels_oc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -74,7 +74,9 @@ void factor_1d(int n, double nu, double a, double* lo, double* di, double* up) {
 
 }  // namespace
 
-static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
+// oc_gamma > 0: the plan of the optimal-control system of the wave equation
+// (Section 4) with that regularisation parameter.
+static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out, double oc_gamma = 0.0) {
   out = nullptr;
   if (!pr) { set_error("problem is NULL"); return PD_ERR_INVALID; }
   const paradiag_problem& p = *pr;
@@ -91,7 +93,17 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
   const bool hybrid = p.scheme == PD_HYBRID || p.scheme == PD_HYBRID_WAVE;
   if (p.prec < 0 || p.prec > 3) { set_error("unknown precision"); return PD_ERR_INVALID; }
   if (p.reserved != 0) { set_error("reserved must be 0"); return PD_ERR_INVALID; }
-  if (hybrid) {
+  const bool oc = oc_gamma > 0.0;
+  if (oc) {
+    if (p.scheme != PD_LEAPFROG || p.ax != 0.0 || p.ay != 0.0 || p.batch != 1) {
+      set_error("optimal control: implicit leap-frog, zero velocity and batch 1 required"); return PD_ERR_UNSUPPORTED;
+    }
+    if (p.nt % 4 == 0 || p.nt < 3 || p.nt > 4096) {
+      // C2 (the circulant of (1, 0, 1)) is singular when 4 divides nt
+      set_error("optimal control needs nt in [3, 4096] not divisible by 4"); return PD_ERR_UNSUPPORTED;
+    }
+    if (!std::isfinite(oc_gamma)) { set_error("gamma must be finite"); return PD_ERR_INVALID; }
+  } else if (hybrid) {
     if ((p.nt & 1) || p.nt < 4 || p.nt > 4096) {
       set_error("hybrid schemes need an even nt in [4, 4096]"); return PD_ERR_UNSUPPORTED;
     }
@@ -121,16 +133,58 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
   pl->prec = static_cast<Prec>(p.prec);
   Geom& g = pl->g;
   g.B = p.batch; g.nt = p.nt; g.F = hybrid ? p.nt / 2 : p.nt / 2 + 1;
+  if (oc) g.F = 2 * (p.nt / 2 + 1);   // Sigma1 and Sigma2 slices of both fields' half spectra
   g.nx = p.nx; g.ny = p.ny;
   if (p.dim == 2) { g.sx = p.nx; g.sy = p.ny; } else { g.sx = 1; g.sy = p.nx; }
   g.S = (int64_t)p.nx * p.ny;
-  g.N1 = g.S * p.nt;
+  g.N1 = g.S * p.nt * (oc ? 2 : 1);
   g.NA = g.N1 * p.batch;
   g.spec_elems = (int64_t)g.B * g.F * g.sy * 2 * g.sx;
 
   const double dt = p.T / p.nt;
   const double PI = 3.14159265358979323846;
-  if (hybrid) {
+  if (oc) {
+    // Section 4: Fourier symbols of the circulants of (1, -2, 1) and (1, 0, 1),
+    // the per-frequency eigenvalues Sigma = a +- i beta |q| of Thm the4 and the
+    // mixing coefficients; DFT tables of length nt (no power of two)
+    pl->oc = true;
+    pl->oc_gamma = oc_gamma;
+    pl->oc_beta = dt * dt / std::sqrt(oc_gamma);
+    const int Fh = p.nt / 2 + 1;
+    pl->oc_fh = Fh;
+    pl->c1[0] = 1.0; pl->c1[1] = -2.0; pl->c1[2] = 1.0;
+    pl->c2[0] = 0.5 * dt * dt; pl->c2[1] = 0.0; pl->c2[2] = 0.5 * dt * dt;
+    pl->L = 3;
+    pl->theta = 0.5;
+    pl->lam1.resize(2 * Fh);
+    pl->lam2.assign(2 * Fh, cd(0.5 * dt * dt, 0.0));
+    pl->ocmix.resize(3 * (size_t)Fh);
+    for (int n = 0; n < Fh; ++n) {
+      const cd w = std::polar(1.0, -2.0 * PI * n / p.nt);
+      const cd d1 = 1.0 - 2.0 * w + w * w, d2 = 1.0 + w * w;
+      const double a = (d1 / d2).real(), aq = 1.0 / std::abs(d2);
+      const cd E = (1.0 / d2) * std::abs(d2);   // q / |q|
+      pl->lam1[n] = cd(a, pl->oc_beta * aq);
+      pl->lam1[Fh + n] = cd(a, -pl->oc_beta * aq);
+      const cd inv1 = 1.0 / d2, inv2 = cd(0.0, 1.0) * E / std::conj(d2);
+      pl->ocmix[n] = double2{E.real(), -E.imag()};
+      pl->ocmix[Fh + n] = double2{inv1.real(), inv1.imag()};
+      pl->ocmix[2 * Fh + n] = double2{inv2.real(), inv2.imag()};
+    }
+    std::vector<double> wf((size_t)2 * Fh * p.nt), wi((size_t)p.nt * 2 * Fh);
+    for (int n = 0; n < Fh; ++n) {
+      const double wgt = (n == 0 || 2 * n == p.nt) ? 1.0 : 2.0;
+      for (int m = 0; m < p.nt; ++m) {
+        const double ang = 2.0 * PI * (double)(((int64_t)n * m) % p.nt) / p.nt;
+        wf[(size_t)(2 * n) * p.nt + m] = std::cos(ang);
+        wf[(size_t)(2 * n + 1) * p.nt + m] = -std::sin(ang);
+        wi[(size_t)m * 2 * Fh + 2 * n] = wgt / p.nt * std::cos(ang);
+        wi[(size_t)m * 2 * Fh + 2 * n + 1] = -wgt / p.nt * std::sin(ang);
+      }
+    }
+    pl->wf_frag = time_gemm_fragments(wf, 2 * Fh, p.nt);
+    pl->wi_frag = time_gemm_fragments(wi, p.nt, 2 * Fh);
+  } else if (hybrid) {
     // ParaDiag-I: the closed-form eigendecomposition of B (Thm thmCondU)
     pl->hybrid = true;
     pl->order = p.scheme == PD_HYBRID ? 1 : 2;
@@ -139,8 +193,8 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out) {
     if (!hybrid_eigen(p.nt, dt, pl->order, ht, err)) { set_error(err); return PD_ERR_BREAKDOWN; }
     pl->lam1 = ht.d;
     pl->lam2.assign(g.F, cd(1.0, 0.0));
-    pl->wf_frag = time_gemm_fragments(ht.wf, p.nt);
-    pl->wi_frag = time_gemm_fragments(ht.wi, p.nt);
+    pl->wf_frag = time_gemm_fragments(ht.wf, p.nt, p.nt);
+    pl->wi_frag = time_gemm_fragments(ht.wi, p.nt, p.nt);
     pl->band = ht.band;
     pl->band_t.assign(ht.band.size(), 0.0);   // rows of the transpose: (B^T)[r][r+k] = B[r+k][r]
     for (int r = 0; r < p.nt; ++r)
@@ -236,8 +290,13 @@ size_t tables_bytes(const Plan& pl) {
   b += align_up(sizeof(float2) * g.nt);               // twiddles f32
   b += align_up(sizeof(double2) * 2 * g.F);           // lam
   if (pl.hybrid) {
-    b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt));   // V^{-1}, V (fragment order)
+    b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt, g.nt));   // V^{-1}, V (fragment order)
     b += 2 * align_up(sizeof(double) * 5 * g.nt);                         // banded rows of B, B^T
+  }
+  if (pl.oc) {
+    b += align_up(sizeof(double) * time_gemm_fragment_elems(2 * pl.oc_fh, g.nt));   // DFT
+    b += align_up(sizeof(double) * time_gemm_fragment_elems(g.nt, 2 * pl.oc_fh));   // inverse DFT
+    b += align_up(sizeof(double2) * 3 * pl.oc_fh);                                  // mixing
   }
   if (pl.p.dim == 2) {
     const size_t n = g.nx;
@@ -371,6 +430,11 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   const SpaceOp& op = pl.op[variant];
   void* const spec_a = buf_a ? buf_a : pl.spec_a;
   void* const spec_b = buf_b ? buf_b : pl.spec_b;
+  if (pl.oc) {
+    Timed t(pl, PD_STAGE_LINE_SOLVE, s, 8.0 * pl.g.NA * (accumulate ? 3.0 : 2.0), 0.0);
+    oc_apply_prec(pl, in, bscale, out, out_f32, accumulate, spec_a, spec_b, s);
+    return;
+  }
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
   {
@@ -942,6 +1006,22 @@ extern "C" {
 const char* paradiag_last_error(void) { return g_last_error.c_str(); }
 const char* paradiag_version(void) { return "paradiag-gfx950 0.1"; }
 
+paradiag_status paradiag_oc_setup(const paradiag_problem* prob, double gamma, paradiag_plan* out) {
+  if (!out) { set_error("out is NULL"); return PD_ERR_INVALID; }
+  *out = nullptr;
+  if (!(gamma > 0.0)) { set_error("gamma must be positive"); return PD_ERR_INVALID; }
+  try {
+    Plan* pl = nullptr;
+    paradiag_status st = build_plan(prob, pl, gamma);
+    if (st != PD_OK) return st;
+    *out = reinterpret_cast<paradiag_plan>(pl);
+    return PD_OK;
+  } catch (...) {
+    set_error("out of host memory");
+    return PD_ERR_INVALID;
+  }
+}
+
 paradiag_status paradiag_setup(const paradiag_problem* prob, paradiag_plan* out) {
   if (!out) { set_error("out is NULL"); return PD_ERR_INVALID; }
   *out = nullptr;
@@ -1025,8 +1105,17 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
     }
     up(pl->d_lam, lam.data(), sizeof(double2) * 2 * g.F);
   }
+  if (pl->oc) {
+    const size_t f1 = time_gemm_fragment_elems(2 * pl->oc_fh, g.nt), f2 = time_gemm_fragment_elems(g.nt, 2 * pl->oc_fh);
+    pl->d_wf = (double*)take(sizeof(double) * f1);
+    pl->d_wi = (double*)take(sizeof(double) * f2);
+    pl->d_ocmix = (double2*)take(sizeof(double2) * 3 * pl->oc_fh);
+    up(pl->d_wf, pl->wf_frag.data(), sizeof(double) * f1);
+    up(pl->d_wi, pl->wi_frag.data(), sizeof(double) * f2);
+    up(pl->d_ocmix, pl->ocmix.data(), sizeof(double2) * 3 * pl->oc_fh);
+  }
   if (pl->hybrid) {
-    const size_t fe = time_gemm_fragment_elems(g.nt);
+    const size_t fe = time_gemm_fragment_elems(g.nt, g.nt);
     pl->d_wf = (double*)take(sizeof(double) * fe);
     pl->d_wi = (double*)take(sizeof(double) * fe);
     pl->d_band = (double*)take(sizeof(double) * 5 * g.nt);
@@ -1147,8 +1236,19 @@ paradiag_status paradiag_build_rhs(paradiag_plan plan, const double* U0, const d
   Plan* pl = ready(plan);
   if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
   if (!U0 || !b) { set_error("U0 and b are required"); return PD_ERR_INVALID; }
+  if (pl->oc) { set_error("optimal-control plans build their right-hand side with paradiag_oc_build_rhs"); return PD_ERR_UNSUPPORTED; }
   build_rhs(*pl, U0, (pl->p.scheme == PD_LEAPFROG || pl->p.scheme == PD_HYBRID_WAVE) ? u1 : nullptr, f, b, (hipStream_t)stream);
   return check_hip("build_rhs");
+}
+
+paradiag_status paradiag_oc_build_rhs(paradiag_plan plan, const double* U0, const double* u1,
+                                      const double* f, const double* g, double* b, void* stream) {
+  Plan* pl = ready(plan);
+  if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
+  if (!pl->oc) { set_error("not an optimal-control plan"); return PD_ERR_INVALID; }
+  if (!U0 || !b) { set_error("U0 and b are required"); return PD_ERR_INVALID; }
+  oc_build_rhs(*pl, U0, u1, f, g, b, (hipStream_t)stream);
+  return check_hip("oc_build_rhs");
 }
 
 paradiag_status paradiag_rhs_transpose(paradiag_plan plan, const double* lam, double* gU0,
@@ -1156,7 +1256,7 @@ paradiag_status paradiag_rhs_transpose(paradiag_plan plan, const double* lam, do
   Plan* pl = ready(plan);
   if (!pl) return plan ? PD_ERR_WORKSPACE : PD_ERR_INVALID;
   if (!lam || !gU0) { set_error("lam and gU0 are required"); return PD_ERR_INVALID; }
-  if (pl->hybrid) { set_error("rhs_transpose is not provided for the hybrid schemes"); return PD_ERR_UNSUPPORTED; }
+  if (pl->hybrid || pl->oc) { set_error("rhs_transpose is not provided for this plan"); return PD_ERR_UNSUPPORTED; }
   rhs_transpose(*pl, lam, gU0, gu1, gf, (hipStream_t)stream);
   return check_hip("rhs_transpose");
 }
@@ -1168,6 +1268,7 @@ paradiag_status paradiag_matvec(paradiag_plan plan, const double* u, double* y, 
   if (!u || !y) { set_error("NULL vector"); return PD_ERR_INVALID; }
   size_t nb = sizeof(double) * (size_t)pl->g.NA;
   if (overlap(u, nb, y, nb)) { set_error("u and y overlap"); return PD_ERR_INVALID; }
+  if (pl->oc && transpose) { set_error("the transpose of the optimal-control operator is not provided"); return PD_ERR_UNSUPPORTED; }
   apply_A(*pl, transpose ? 1 : 0, u, false, nullptr, y, (hipStream_t)stream);
   return check_hip("matvec");
 }
@@ -1194,6 +1295,7 @@ static paradiag_status solve_entry(paradiag_plan plan, int variant, const double
     set_error("restart must be in [1, 32]"); return PD_ERR_INVALID;
   }
   if (opts->max_iter < 1 || !(opts->rtol > 0)) { set_error("max_iter >= 1 and rtol > 0 required"); return PD_ERR_INVALID; }
+  if (pl->oc && variant != 0) { set_error("no adjoint solve for optimal-control plans"); return PD_ERR_UNSUPPORTED; }
   if (pl->hybrid && (variant != 0 || opts->mode == PD_MODE_FGMRES)) {
     set_error("hybrid schemes (ParaDiag-I) solve in the direct and stationary modes only");
     return PD_ERR_UNSUPPORTED;

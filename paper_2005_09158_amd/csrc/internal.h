@@ -148,6 +148,15 @@ struct Plan {
   // of the time matrix and of its transpose for the matvec
   bool hybrid = false;
   int order = 1;
+  // optimal control of the wave equation (Section 4): Fh = nt/2 + 1 frequencies
+  // per field, g.F = 2 Fh spectral slices (Sigma1 block, then Sigma2 block),
+  // vectors of 2 nt S values; per-frequency mixing coefficients conj(E),
+  // 1/d2 and i E / conj(d2) (double2 each, d_ocmix: [3][Fh])
+  bool oc = false;
+  int oc_fh = 0;
+  double oc_gamma = 0.0, oc_beta = 0.0;
+  std::vector<double2> ocmix;
+  double2* d_ocmix = nullptr;
   std::vector<double> wf_frag, wi_frag, band, band_t;
   // host staging of the shifted time symbols of the nonlinear solver (kept
   // alive until the plan is destroyed: an asynchronous copy reads it)
@@ -192,8 +201,16 @@ void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, 
 // (x float64 [B][nt][S]), inverse z (+)= V spec (z float64 or float32).
 void time_transform(const Plan& pl, bool forward, const void* in, void* out, bool out_f32,
                     int accumulate, hipStream_t s);
-std::vector<double> time_gemm_fragments(const std::vector<double>& W, int nt);
-size_t time_gemm_fragment_elems(int nt);
+// Dense time products C[b] = W X[b] on MFMA (float64): forward reads real data
+// [batch][nt][S] and writes m spectral rows (2 per frequency, F frequencies per
+// batch entry, planar layout); the inverse reads k = 2F' spectral rows and
+// writes (or adds to, accumulate) m = nt real rows.  `table` holds W (m x k) in
+// the fragment order of time_gemm_fragments.
+void time_gemm(const Plan& pl, bool forward, const double* table, const void* in, void* out, bool spec_f32,
+               bool out_f32, int accumulate, int batch, int nt, int F, int m, int k, hipStream_t s,
+               const double* cscale = nullptr);
+std::vector<double> time_gemm_fragments(const std::vector<double>& W, int m, int k);
+size_t time_gemm_fragment_elems(int m, int k);
 // Step-(b) pieces
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
            hipStream_t s);
@@ -220,8 +237,23 @@ void rhs_transpose(const Plan& pl, const double* lam, double* gU0, double* gu1, 
 // Krylov helpers (float64).  Vectors of one batch entry are N1 long and the
 // batch stride of every vector is N1.
 int dot_chunks(const Plan& pl);
+// slot0: first partial-sum slot written (dots land in slots slot0 .. slot0 + nv - 1)
 void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* w,
-               double* partial, hipStream_t s);
+               double* partial, hipStream_t s, int slot0 = 0);
+// y = A u (or b - A u) of one field of nt * S values with the plan's Toeplitz
+// columns and stencil, no dots (transpose: A^T)
+void matvec_plain(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
+                  double* y, int transpose, hipStream_t s);
+// Optimal control of the wave equation (vectors [2][nt][S]: sqrt(gamma) u, p):
+// y = A u (or b - A u) with the Krylov dots of matvec's interface, and
+// z (+)= P^{-1} r (Thm the4) with the spectral buffers sa, sb
+void oc_matvec(const Plan& pl, const void* u, bool u_is_f32, const double* b, double* y, hipStream_t s,
+               const double* Vk, int64_t vstride, int nv, double* partial, int sq, const double* V0,
+               int v0sq);
+void oc_apply_prec(const Plan& pl, const double* in, const double* scale, void* out, bool out_f32,
+                   int accumulate, void* sa, void* sb, hipStream_t s);
+void oc_build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, const double* gsrc,
+                  double* b, hipStream_t s);
 // h[b][i] = t s, coef[b][i] = t s^2 with t the reduced dot and s = sigma[b][i]
 // for i < nscaled (else 1): dots against unnormalised Krylov vectors.
 // chunks: partial sums per right-hand side (<= 0: dot_chunks).  hhost

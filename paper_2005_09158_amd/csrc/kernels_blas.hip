@@ -472,7 +472,7 @@ __global__ __launch_bounds__(NT) void k_last_rows(const double* __restrict__ src
 template <int NV>
 __global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int64_t vstride, int nv,
                                                const double* __restrict__ w, double* __restrict__ partial,
-                                               int64_t N1, int chunks) {
+                                               int64_t N1, int chunks, int slot0) {
   __shared__ double red[4];
   constexpr int NR = NV > 0 ? NV : MAXV;
   const int b = blockIdx.y, c = blockIdx.x;
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_mdot_t(const double* __restrict__ V, int
         acc[i] += v.x * wv.x + v.y * wv.y;
       }
   }
-  double* out = partial + ((int64_t)b * chunks + c) * MAXV;
+  double* out = partial + ((int64_t)b * chunks + c) * MAXV + slot0;
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
     if (NV > 0 || i < nv) {  // nv is uniform: the barrier inside is reached by all threads
@@ -737,9 +737,26 @@ static dim3 matvec_grid(const Plan& pl, int& V, int& chunk) {
 }
 
 int matvec_chunks(const Plan& pl) {
+  if (pl.oc) return dot_chunks(pl);   // its dots come from multi_dot
   int V, chunk;
   const dim3 gr = matvec_grid(pl, V, chunk);
   return (int)(gr.x * gr.y);
+}
+
+void matvec_plain(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
+                  double* y, int transpose, hipStream_t s) {
+  int V, chunk;
+  const dim3 grid = matvec_grid(pl, V, chunk);
+  Stencil st = stencil_of(op);
+  const int dir = transpose ? -1 : 1;
+  const Geom& g = pl.g;
+#define PD_MVP(TIN, VV)                                                                            \
+  k_matvec<TIN, VV, 0><<<grid, NT, 0, s>>>((const TIN*)u, b, y, g.nt, g.nx, g.ny, pl.L, pl.c1[0],  \
+                                           pl.c1[1], pl.c1[2], pl.c2[0], pl.c2[1], pl.c2[2], st,  \
+                                           chunk, dir, nullptr, 0, 0, 0, nullptr, nullptr, 0)
+  if (u_is_f32) { if (V == 4) PD_MVP(float, 4); else PD_MVP(float, 1); }
+  else { if (V == 4) PD_MVP(double, 4); else PD_MVP(double, 1); }
+#undef PD_MVP
 }
 
 void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, const double* b,
@@ -750,6 +767,10 @@ void matvec(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f32, con
   Stencil st = stencil_of(op);
   int dir = transpose ? -1 : 1;
   const Geom& g = pl.g;
+  if (pl.oc) {
+    oc_matvec(pl, u, u_is_f32, b, y, s, Vk, vstride, nv, partial, sq, V0, v0sq);
+    return;
+  }
   if (pl.hybrid) {   // banded time matrix; Krylov dots are not fused here
     const double* band = transpose ? pl.d_band_t : pl.d_band;
 #define PD_MVB(TIN, VV) \
@@ -808,14 +829,14 @@ int dot_chunks(const Plan& pl) {
 }
 
 void multi_dot(const Plan& pl, const double* V, int64_t vstride, int nv, const double* w,
-               double* partial, hipStream_t s) {
+               double* partial, hipStream_t s, int slot0) {
   int chunks = dot_chunks(pl);
   dim3 grid(chunks, pl.g.B);
   switch (nv) {
-#define PD_MD(K) case K: k_mdot_t<K><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks); return;
+#define PD_MD(K) case K: k_mdot_t<K><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks, slot0); return;
     PD_MD(1) PD_MD(2) PD_MD(3) PD_MD(4) PD_MD(5) PD_MD(6) PD_MD(7) PD_MD(8)
 #undef PD_MD
-    default: k_mdot_t<0><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks);
+    default: k_mdot_t<0><<<grid, NT, 0, s>>>(V, vstride, nv, w, partial, pl.g.N1, chunks, slot0);
   }
 }
 

@@ -50,7 +50,7 @@ template <typename Tx, typename Tc, int FM, bool FWD>
 __global__ __launch_bounds__(NT) void k_time_gemm(const double* __restrict__ Wf, const Tx* __restrict__ X,
                                                   Tc* __restrict__ C, int M, int K, int Kpad, int64_t S,
                                                   int sx, int64_t xbatch, int64_t cbatch, int ntm,
-                                                  int ntn, int acc_out) {
+                                                  int ntn, int acc_out, const double* __restrict__ cscale) {
   constexpr int BM = 64 * FM;
   __shared__ __align__(16) double Xs[2][BK * LDB];
   const unsigned total = (unsigned)(ntm * ntn) * gridDim.y;
@@ -134,7 +134,9 @@ __global__ __launch_bounds__(NT) void k_time_gemm(const double* __restrict__ Wf,
       buf ^= 1;
     }
   }
-  // epilogue: C[m][j], m = row of this lane, j = point of this lane
+  // epilogue: C[m][j], m = row of this lane, j = point of this lane (times
+  // *cscale when given: the Krylov scale of the input vector)
+  const double sc = cscale ? *cscale : 1.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -146,11 +148,11 @@ __global__ __launch_bounds__(NT) void k_time_gemm(const double* __restrict__ Wf,
         const int m = tm * BM + (wave * FM + i) * 16 + lk + 4 * v;
         if (m >= M) continue;
         if constexpr (FWD) {
-          Cb[spec_off(m, (int)j, sx, S)] = (Tc)acc[i][c][v];
+          Cb[spec_off(m, (int)j, sx, S)] = (Tc)(sc * acc[i][c][v]);
         } else {
           Tc* dst = Cb + (int64_t)m * S + j;
           const double prev = acc_out ? (double)*dst : 0.0;
-          *dst = (Tc)(prev + acc[i][c][v]);
+          *dst = (Tc)(prev + sc * acc[i][c][v]);
         }
       }
     }
@@ -158,51 +160,51 @@ __global__ __launch_bounds__(NT) void k_time_gemm(const double* __restrict__ Wf,
 
 }  // namespace
 
-int time_gemm_rows(int nt) { return nt >= 256 ? 256 : 64; }
+int time_gemm_rows(int m) { return m >= 256 ? 256 : 64; }
 
-// W (nt x nt, row-major) in MFMA fragment order for workgroups of `rows`
-// rows: frag[(rb * (Kpad/4) + ks) * 64 + lane] = W[16 rb + lane % 16][4 ks + lane / 16],
-// zero outside the matrix; Mpad = rows * ceil(nt / rows), Kpad = 16 ceil(nt / 16).
-std::vector<double> time_gemm_fragments(const std::vector<double>& W, int nt) {
-  const int rows = time_gemm_rows(nt);
-  const int Mpad = rows * ((nt + rows - 1) / rows), Kpad = BK * ((nt + BK - 1) / BK);
+// W (m x k, row-major) in MFMA fragment order for workgroups of
+// time_gemm_rows(m) rows: frag[(rb * (Kpad/4) + ks) * 64 + lane] =
+// W[16 rb + lane % 16][4 ks + lane / 16], zero outside the matrix;
+// Mpad = rows * ceil(m / rows), Kpad = 16 ceil(k / 16).
+std::vector<double> time_gemm_fragments(const std::vector<double>& W, int m, int k) {
+  const int rows = time_gemm_rows(m);
+  const int Mpad = rows * ((m + rows - 1) / rows), Kpad = BK * ((k + BK - 1) / BK);
   std::vector<double> f((size_t)Mpad * Kpad, 0.0);
   const int kq = Kpad / 4;
   for (int rb = 0; rb < Mpad / 16; ++rb)
     for (int ks = 0; ks < kq; ++ks)
       for (int l = 0; l < 64; ++l) {
-        const int m = 16 * rb + (l & 15), k = 4 * ks + (l >> 4);
-        if (m < nt && k < nt) f[((size_t)rb * kq + ks) * 64 + l] = W[(size_t)m * nt + k];
+        const int r = 16 * rb + (l & 15), c = 4 * ks + (l >> 4);
+        if (r < m && c < k) f[((size_t)rb * kq + ks) * 64 + l] = W[(size_t)r * k + c];
       }
   return f;
 }
 
-size_t time_gemm_fragment_elems(int nt) {
-  const int rows = time_gemm_rows(nt);
-  return (size_t)(rows * ((nt + rows - 1) / rows)) * (BK * ((nt + BK - 1) / BK));
+size_t time_gemm_fragment_elems(int m, int k) {
+  const int rows = time_gemm_rows(m);
+  return (size_t)(rows * ((m + rows - 1) / rows)) * (BK * ((k + BK - 1) / BK));
 }
 
-void time_transform(const Plan& pl, bool forward, const void* in, void* out, bool out_f32,
-                    int accumulate, hipStream_t s) {
+void time_gemm(const Plan& pl, bool forward, const double* table, const void* in, void* out, bool spec_f32,
+               bool out_f32, int accumulate, int batch, int nt, int F, int m, int k, hipStream_t s,
+               const double* cscale) {
   const Geom& g = pl.g;
-  const int nt = g.nt, rows = time_gemm_rows(nt);
-  const int Kpad = BK * ((nt + BK - 1) / BK);
-  const int ntm = (nt + rows - 1) / rows;
+  const int rows = time_gemm_rows(m);
+  const int Kpad = BK * ((k + BK - 1) / BK);
+  const int ntm = (m + rows - 1) / rows;
   const int ntn = (int)((g.S + BN - 1) / BN);
-  const int64_t tb = (int64_t)nt * g.S, sb = (int64_t)g.F * 2 * g.S;
-  dim3 grid((unsigned)(ntm * ntn), g.B);
-  const bool f64 = pl.prec == Prec::F64;
-#define PD_TG(TX, TC, FM, FW)                                                                      \
-  k_time_gemm<TX, TC, FM, FW><<<grid, NT, 0, s>>>(forward ? pl.d_wf : pl.d_wi, (const TX*)in,    \
-                                                  (TC*)out, nt, nt, Kpad, g.S, g.sx,             \
-                                                  FW ? tb : sb, FW ? sb : tb, ntm, ntn, accumulate)
+  const int64_t tb = (int64_t)nt * g.S, sb = (int64_t)F * 2 * g.S;
+  dim3 grid((unsigned)(ntm * ntn), batch);
+#define PD_TG(TX, TC, FM, FW)                                                                       \
+  k_time_gemm<TX, TC, FM, FW><<<grid, NT, 0, s>>>(table, (const TX*)in, (TC*)out, m, k, Kpad, g.S, g.sx, \
+                                                  FW ? tb : sb, FW ? sb : tb, ntm, ntn, accumulate, cscale)
 #define PD_TG_FM(TX, TC, FW) \
   if (rows == 256) PD_TG(TX, TC, 4, FW); else PD_TG(TX, TC, 1, FW);
   if (forward) {
-    if (f64) { PD_TG_FM(double, double, true) }
+    if (!spec_f32) { PD_TG_FM(double, double, true) }
     else { PD_TG_FM(double, float, true) }
   } else {
-    if (f64) {
+    if (!spec_f32) {
       if (out_f32) { PD_TG_FM(double, float, false) } else { PD_TG_FM(double, double, false) }
     } else {
       if (out_f32) { PD_TG_FM(float, float, false) } else { PD_TG_FM(float, double, false) }
@@ -210,6 +212,13 @@ void time_transform(const Plan& pl, bool forward, const void* in, void* out, boo
   }
 #undef PD_TG_FM
 #undef PD_TG
+}
+
+void time_transform(const Plan& pl, bool forward, const void* in, void* out, bool out_f32,
+                    int accumulate, hipStream_t s) {
+  const Geom& g = pl.g;
+  time_gemm(pl, forward, forward ? pl.d_wf : pl.d_wi, in, out, pl.prec != Prec::F64, out_f32, accumulate,
+            g.B, g.nt, g.F, g.nt, g.nt, s);
 }
 
 }  // namespace pd

@@ -1,0 +1,111 @@
+"""GPU parity of the optimal control of the wave equation (Section 4).
+
+The library's operator (two leap-frog marches and the field coupling), its
+block-circulant preconditioner (Thm the4: DFT products on MFMA, the 2 x 2
+mixing, shifted solves, unmixing with C2^{-1}) and the right-hand side of the
+paper's example are compared with the oracle (``oracle.ocwave``): the operator
+and the right-hand side to 1e-13 (a few float64 operations per entry), the
+preconditioner to 1e-11 (the DFTs are O(Nt) sums and the mixing matrices are
+perfectly conditioned, so the error is that of the shifted solves).  Flexible
+GMRES with P to 1e-7 must take the iteration counts of Table T2A, at the
+table's sizes up to (256, 256, 257) in the launch configuration bench.py uses.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import ocwave
+from tests.conftest import load_golden
+from tests.gpu_util import announce, rel_err, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(n, nt, gamma, prec="fp64", dim=2, restart=30):
+    from paper_2005_09158_amd import ParaDiagOC
+    ny = n - 1 if dim == 2 else 1
+    return ParaDiagOC(dim=dim, nx=n - 1, ny=ny, nt=nt, T=2.0, nu=1.0, gamma=gamma, prec=prec, restart=restart)
+
+
+def _oprob(n, nt, dim=2):
+    p = ocwave.wave_problem(n, nt)
+    if dim == 1:
+        from oracle import Problem
+        p = Problem(dim=1, nx=n - 1, ny=1, nt=nt, scheme="lf", T=2.0, nu=1.0)
+    return p
+
+
+@pytest.mark.parametrize("n,nt,dim", [(12, 17, 2), (10, 18, 2), (20, 9, 2), (40, 33, 1)])
+def test_oc_operator_and_preconditioner(n, nt, dim):
+    announce(f"oc operator/precond N={n} Nt={nt} dim={dim}")
+    torch = torch_gpu()
+    gamma = 1e-4
+    pd = _plan(n, nt, gamma, dim=dim)
+    p = _oprob(n, nt, dim)
+    x = np.random.default_rng(n + nt).standard_normal(2 * nt * p.nspace)
+    xg = torch.from_numpy(x).reshape(pd.shape).cuda()
+    y = pd.matvec(xg).cpu().numpy().ravel()
+    assert rel_err(y, ocwave.assembled(p, gamma) @ x) < 1e-13
+    z = pd.apply_precond(xg).cpu().numpy().ravel()
+    zr = ocwave.apply_P_inverse(p, gamma, x)
+    err = rel_err(z, zr)
+    print(f"  P^-1 rel err {err:.2e}")
+    assert err < 1e-11
+    if p.nspace * nt <= 4000:
+        zd = np.linalg.solve(ocwave.assembled(p, gamma, circulant=True).toarray(), x)
+        assert rel_err(z, zd) < 1e-11
+
+
+def _example_rhs(torch, pd, n, nt, gamma, T=2.0):
+    """The library's right-hand side of Section 4's example, whose exact
+    solution is u = e^t sin(pi x) sin(pi y), p = (t - T)^2 sin(pi x) sin(pi y)."""
+    x = np.arange(1, n) / n
+    s = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+    t = np.arange(nt + 1) * (T / nt)
+    f = ((1 + 2 * np.pi ** 2) * np.exp(t) - (t - T) ** 2 / gamma)[:, None, None] * s[None]
+    g = (np.exp(t) + 2 + 2 * np.pi ** 2 * (t - T) ** 2)[:, None, None] * s[None]
+    cu = lambda a, shp: torch.from_numpy(np.ascontiguousarray(a)).reshape(shp).cuda()
+    return pd.build_rhs(cu(s, pd.field_shape), cu(s, pd.field_shape), cu(f, pd.source_shape),
+                        cu(g, pd.source_shape))
+
+
+def test_oc_build_rhs():
+    announce("oc right-hand side of the paper's example")
+    torch = torch_gpu()
+    n, nt, gamma = 16, 17, 1e-6
+    pd = _plan(n, nt, gamma)
+    p = ocwave.wave_problem(n, nt)
+    b = _example_rhs(torch, pd, n, nt, gamma).cpu().numpy().ravel()
+    assert rel_err(b, ocwave.rhs(p, gamma)) < 1e-13
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+def test_oc_fgmres_iterations_table_t2a(n):
+    """Iteration counts of Table T2A on the GPU (right-preconditioned flexible
+    GMRES, restart 30, true relative residual 1e-7); the oracle's GMRES takes
+    the same counts for N <= 64 (tests/test_oracle_ocwave.py), and for N <= 32
+    the GPU solution is compared with the oracle's solve."""
+    announce(f"oc FGMRES N={n}")
+    torch = torch_gpu()
+    rows = {r["N"]: r for r in load_golden("table_t2a.json")["rows"]}
+    p = ocwave.wave_problem(n, n + 1)
+    for gamma, key in ((1e-2, "g1e-2"), (1e-4, "g1e-4"), (1e-6, "g1e-6"), (1e-8, "g1e-8"), (1e-10, "g1e-10")):
+        pd = _plan(n, n + 1, gamma)
+        # the oracle's right-hand side where it is quick, else the library's
+        # (equal to it within 1e-13, test_oc_build_rhs)
+        if n <= 64:
+            b = torch.from_numpy(ocwave.rhs(p, gamma)).reshape(pd.shape).cuda()
+        else:
+            b = _example_rhs(torch, pd, n, n + 1, gamma)
+        u, res = pd.solve(b, rtol=1e-7, max_iter=60, restart=30)
+        print(f"  N {n} gamma {gamma}: {res.iters} iterations (printed {rows[n][key]}), resid {res.rel_resid:.2e}",
+              flush=True)
+        assert res.converged and res.rel_resid <= 1e-7
+        assert abs(res.iters - rows[n][key]) <= 1
+        if n <= 32:
+            x = ocwave.solve(p, gamma, b.cpu().numpy().ravel())
+            # the solve error is at most cond(A) times the residual; compare loosely
+            assert rel_err(u.cpu().numpy().ravel(), x) < 1e-3
+        del pd, b, u
+        torch.cuda.empty_cache()
