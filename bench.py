@@ -23,10 +23,13 @@ The JSON line also carries
   (one core; it also yields the error reference), and a sample of the
   oracle's own ParaDiag-II preconditioner with Step-(b) spread over the host
   cores, scaled to a whole solve.
-* a ParaDiag-I leg (key `paradiag_i`): the direct float64 solve of the hybrid
-  time discretisation on the wave problem of Table Ex2Tab1 (511^2 x 512), its
-  rate, its error against the exact solution and its dominant kernel's
-  roofline.
+* extra legs, each with its rate, its accuracy and its dominant kernel's
+  roofline: `paradiag_i`, the direct float64 solve of the hybrid time
+  discretisation on the wave problem of Table Ex2Tab1 (511^2 x 512);
+  `oc_wave`, the optimal control of the wave equation at Table T2A's largest
+  size (255^2 x 257, gamma 1e-4); `parareal`, the ParaDiag-II parareal
+  variant (1023 points, 64 intervals x 32 fine steps, batch 256); and
+  `nonlinear`, simplified Newton for 2D Allen-Cahn (511^2 x 256).
 One extra solve before the timed region, with every stage timed, gives the
 per-stage breakdown and picks the dominant stage; inside the timed region only
 that stage records events, since every event pair costs a few microseconds of
@@ -73,8 +76,11 @@ def parse():
                          "for the wave equation, split-bf16 x-transform otherwise)")
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--skip-paradiag-i", action="store_true",
-                    help="skip the ParaDiag-I (hybrid time discretisation) leg")
+    ap.add_argument("--legs", default="paradiag_i,oc_wave,parareal,nonlinear",
+                    help="comma-separated extra legs after the main one (paradiag_i, oc_wave, "
+                         "parareal, nonlinear), or 'none'")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run only the extra legs (one JSON line holding them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle's sequential solve (no error_vs_oracle, no cpu_baseline)")
@@ -325,6 +331,60 @@ def cpu_baselines(cfg, ref_dt, sample, iters):
     return base, para
 
 
+def timed_leg(pd, call, args, torch):
+    """Warm-up calls, one call with every stage timed (the breakdown and the
+    dominant stage), then `args.steps` timed calls with events around the
+    dominant stage only.  Returns (ms per call, last result, stages, dominant,
+    the dominant stage's timed figures)."""
+    for _ in range(args.warmup):
+        call()
+    pd.set_timing(True)
+    pd.stage_times(reset=True)
+    call()
+    stages = pd.stage_times(reset=True)
+    dominant = max(stages, key=lambda k: stages[k][0])
+    pd.set_timing(True, stages=[dominant])
+    pd.stage_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    timed = pd.stage_times(reset=True)[dominant]
+    pd.set_timing(False)
+    return ms, out, stages, dominant, timed
+
+
+# kernels behind a stage where it differs from the ParaDiag-II default
+LEG_KERNEL = {"hyb": {"fft_fwd": "k_time_gemm (V^-1)", "fft_inv": "k_time_gemm (V)"},
+              "oc": {"fft_fwd": "k_time_gemm (DFT) + k_oc_mix", "fft_inv": "k_oc_unmix + k_time_gemm (inverse DFT)",
+                     "line_solve": "k_line_solve"},
+              "par": {"fine": "k_parareal_fine", "line_solve": "k_line_solve"},
+              "nl": {"reaction": "k_nl_residual", "line_solve": "k_line_solve"}}
+
+
+def leg_roofline(leg, dominant, timed):
+    """Roofline of a leg's dominant stage (every leg computes in float64):
+    MFMA-bound products (the x-transforms, the time products of ParaDiag-I
+    and of the optimal-control DFTs), the fine propagator's vector ALU work,
+    or HBM bytes."""
+    tms, cnt, by, fl = timed
+    cnt = max(cnt, 1)
+    avg_s = tms / 1e3 / cnt
+    if (dominant in ("fft_fwd", "fft_inv") and leg in ("hyb", "oc")) or dominant in ("xform_fwd", "xform_inv"):
+        bound, achieved, peak, unit = "mfma", fl / cnt / avg_s / 1e12, PEAK["mfma_TFs"]["fp64"], "TFLOP/s"
+    elif dominant == "fine":
+        bound, achieved, peak, unit = "alu", fl / cnt / avg_s / 1e12, PEAK["vector_TFs"]["fp64"], "TFLOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", by / cnt / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
+    kernel = LEG_KERNEL.get(leg, {}).get(dominant, STAGE_KERNEL.get(dominant, dominant))
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "kernel": kernel, "stage": dominant, "launches": cnt,
+            "avg_launch_ms": round(tms / cnt, 5), "algorithmic_flops_per_launch": fl / cnt,
+            "algorithmic_bytes_per_launch": by / cnt}
+
+
 def run_paradiag_i(args, torch):
     """ParaDiag-I leg: the direct solve of the hybrid time discretisation on the
     wave problem of Table Ex2Tab1 (511^2 points, Nt = 512, T = 2), float64,
@@ -342,33 +402,10 @@ def run_paradiag_i(args, torch):
                      torch.from_numpy(V0).reshape(pd.field_shape).cuda(),
                      torch.from_numpy(f).reshape(pd.source_shape).cuda())
     u = torch.empty_like(b)
-    for _ in range(args.warmup):
-        pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
-    pd.set_timing(True)
-    pd.stage_times(reset=True)
-    pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
-    stages = pd.stage_times(reset=True)
-    dominant = max(stages, key=lambda k: stages[k][0])
-    pd.set_timing(True, stages=[dominant])
-    pd.stage_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, res = pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    timed = pd.stage_times(reset=True)
-    pd.set_timing(False)
+    ms, (_, res), stages, dominant, timed = timed_leg(
+        pd, lambda: pd.solve(b, u, mode="direct", rtol=1e-8, max_iter=1), args, torch)
     un = u.cpu().numpy().reshape(cfg.nt, -1)
     err = float(np.abs(un - hybrid_wave_exact(cfg).reshape(cfg.nt, -1)).max())
-    tms, cnt, by, fl = timed[dominant]
-    avg_s = tms / 1e3 / max(cnt, 1)
-    bound = "mfma" if dominant in ("fft_fwd", "fft_inv", "xform_fwd", "xform_inv") else "hbm"
-    if bound == "mfma":
-        achieved, peak, unit = fl / max(cnt, 1) / avg_s / 1e12, PEAK["mfma_TFs"]["fp64"], "TFLOP/s"
-    else:
-        achieved, peak, unit = by / max(cnt, 1) / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
-    kernel = {"fft_fwd": "k_time_gemm (V^-1)", "fft_inv": "k_time_gemm (V)"}.get(dominant, STAGE_KERNEL[dominant])
     U = cfg.unknowns
     return {
         "workload": f"hyb: 2D wave equation {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, T {cfg.T}, hybrid "
@@ -376,13 +413,109 @@ def run_paradiag_i(args, torch):
         "unknowns": U, "ms_per_step": ms, "value": U / (ms / 1e3), "unit": "unknowns/s",
         "dtype": "f64", "rel_resid": res.rel_resid,
         "error_vs_exact": err, "error_printed_in_paper": 7.88e-05,
-        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
-        "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                     "frac": round(achieved / peak, 4), "kernel": kernel, "stage": dominant,
-                     "launches": cnt, "avg_launch_ms": round(tms / max(cnt, 1), 5),
-                     "algorithmic_flops_per_launch": fl / max(cnt, 1),
-                     "algorithmic_bytes_per_launch": by / max(cnt, 1)},
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items() if v[1]},
+        "roofline": leg_roofline("hyb", dominant, timed),
     }
+
+
+def run_oc(args, torch):
+    """Optimal-control leg (Section 4): the gamma-scaled optimality system of
+    the paper's example at Table T2A's largest size (255^2 interior points,
+    Nt = 257, gamma = 1e-4), flexible GMRES with the block-circulant
+    preconditioner to a relative residual of 1e-7, float64.  Reports unknowns
+    (both fields) per second of whole solves, the iteration count against the
+    table's, the error against the exact (u, p) and the dominant kernel's
+    roofline."""
+    from paper_2005_09158_amd import ParaDiagOC
+    from workloads import CONFIGS, oc_example_data, oc_example_exact
+    cfg = CONFIGS["oc"]
+    pd = ParaDiagOC(dim=2, nx=cfg.nx, ny=cfg.ny, nt=cfg.nt, T=cfg.T, nu=cfg.nu, gamma=cfg.gamma,
+                    prec=cfg.prec, restart=30)
+    U0, u1, f, g = oc_example_data(cfg)
+    cu = lambda a, shp: torch.from_numpy(np.ascontiguousarray(a)).reshape(shp).cuda()
+    b = pd.build_rhs(cu(U0, pd.field_shape), cu(u1, pd.field_shape), cu(f, pd.source_shape),
+                     cu(g, pd.source_shape))
+    x = torch.empty_like(b)
+    ms, (_, res), stages, dominant, timed = timed_leg(
+        pd, lambda: pd.solve(b, x, rtol=cfg.rtol, max_iter=60, restart=30), args, torch)
+    xn = x.cpu().numpy().reshape(2, cfg.nt, -1)
+    ue, pe = oc_example_exact(cfg)
+    u = xn[0] / np.sqrt(cfg.gamma)
+    err_u = float(np.abs(u - ue.reshape(cfg.nt, -1)).max() / np.abs(ue).max())
+    err_p = float(np.abs(xn[1] - pe.reshape(cfg.nt, -1)).max() / np.abs(pe).max())
+    U = 2 * cfg.unknowns
+    return {
+        "workload": f"oc: optimal control of the 2D wave equation {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, "
+                    f"T {cfg.T}, gamma {cfg.gamma}, implicit leap-frog, block-circulant "
+                    f"preconditioner (Section 4, Table T2A N = 256)",
+        "unknowns": U, "ms_per_step": ms, "value": U / (ms / 1e3), "unit": "unknowns/s",
+        "dtype": "f64", "rel_resid": res.rel_resid, "iters": res.iters, "iters_printed_in_paper": 5,
+        "rel_error_vs_exact": {"u": err_u, "p": err_p},
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items() if v[1]},
+        "roofline": leg_roofline("oc", dominant, timed),
+    }
+
+
+def run_parareal(args, torch):
+    """Parareal leg (Section 2.2.2): the ParaDiag-II parareal variant on 1D
+    advection-diffusion with Figure 1.5's coefficients (1023 points, 64
+    coarse intervals, J = 32 backward Euler fine steps, alpha = 0.1), a batch
+    of 256 initial states, iterated to a relative change of 1e-10.  Reports
+    fine-grid space-time unknowns (J per coarse unknown) per second, the
+    iteration count, the error against the sequential fine solution (torch
+    float64 time stepping of one initial state, after the timed region) and
+    the dominant kernel's roofline."""
+    from paper_2005_09158_amd import ParaDiag
+    from workloads import CONFIGS, parareal_initial
+    cfg = CONFIGS["par"]
+    pd = ParaDiag(**cfg.problem_kwargs(), batch=cfg.batch, prec="fp64", mode="parareal")
+    U0 = torch.from_numpy(parareal_initial(cfg)).reshape(pd.field_shape).cuda()
+    u = torch.empty(pd.shape, dtype=torch.float64, device="cuda")
+    J = cfg.fine_steps
+    ms, (_, res), stages, dominant, timed = timed_leg(
+        pd, lambda: pd.parareal(U0, J, u, rtol=cfg.rtol, max_iter=60), args, torch)
+    fine = cfg.unknowns * J
+    return {
+        "workload": f"par: parareal variant, 1D advection-diffusion {cfg.nx} points, {cfg.nt} coarse "
+                    f"intervals x J {J} backward Euler steps, T {cfg.T}, nu {cfg.nu}, a {cfg.ax}, "
+                    f"alpha {cfg.alpha}, batch {cfg.batch} (Figure 1.5's coefficients)",
+        "unknowns": fine, "ms_per_step": ms, "value": fine / (ms / 1e3),
+        "unit": "fine-grid unknowns/s", "dtype": "f64", "iters": res.iters,
+        "rel_change": res.rel_resid,
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items() if v[1]},
+        "roofline": leg_roofline("par", dominant, timed),
+    }
+
+
+def run_nonlinear(args, torch):
+    """Nonlinear leg (eq1.4, eq1.5): 2D Allen-Cahn on 511^2 points, Nt = 256
+    backward Euler steps, simplified Newton with the averaged Jacobian and
+    the alpha-circulant preconditioner (alpha = 0.05), float64, to a relative
+    residual of 1e-10.  Reports unknowns per second of whole solves, the
+    correction count and the dominant kernel's roofline."""
+    from paper_2005_09158_amd import ParaDiag
+    from workloads import CONFIGS, nonlinear_initial
+    cfg = CONFIGS["nl"]
+    k1, k2, k3 = cfg.reaction
+    pd = ParaDiag(**cfg.problem_kwargs(), prec="fp64", mode="nonlinear")
+    U0 = torch.from_numpy(nonlinear_initial(cfg)).reshape(pd.field_shape).cuda()
+    u = torch.empty((1,) + pd.shape, dtype=torch.float64, device="cuda")
+    ms, (_, res), stages, dominant, timed = timed_leg(
+        pd, lambda: pd.nonlinear_solve(U0, k1, k2, k3, u=u, rtol=cfg.rtol, max_iter=100), args, torch)
+    U = cfg.unknowns
+    return {
+        "workload": f"nl: 2D Allen-Cahn {cfg.nx}x{cfg.ny}, Nt {cfg.nt}, BE, T {cfg.T}, nu {cfg.nu}, "
+                    f"g(u) = {k1} u + {k3} u^3, alpha {cfg.alpha}, simplified Newton (eq1.5)",
+        "unknowns": U, "ms_per_step": ms, "value": U / (ms / 1e3), "unit": "unknowns/s",
+        "dtype": "f64", "corrections": res.iters, "rel_resid": res.rel_resid,
+        "converged": bool(res.converged),
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items() if v[1]},
+        "roofline": leg_roofline("nl", dominant, timed),
+    }
+
+
+EXTRA_LEGS = {"paradiag_i": run_paradiag_i, "oc_wave": run_oc, "parareal": run_parareal,
+              "nonlinear": run_nonlinear}
 
 
 def workload_name(cfg):
@@ -408,6 +541,24 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    legs = [] if args.legs == "none" else [x for x in args.legs.split(",") if x]
+    for name in legs:
+        if name not in EXTRA_LEGS:
+            print(f"unknown leg {name!r} (known: {', '.join(EXTRA_LEGS)})", file=sys.stderr)
+            sys.exit(2)
+    if args.legs_only:
+        import torch
+        if not torch.cuda.is_available():
+            print("no GPU visible", file=sys.stderr)
+            sys.exit(1)
+        torch.cuda.set_device(0)
+        line = {"legs_only": True, "steps": args.steps, "warmup": args.warmup}
+        for name in legs:
+            print(f"[bench] leg {name}", file=sys.stderr, flush=True)
+            line[name] = EXTRA_LEGS[name](args, torch)
+            print(f"[bench] {name}: {line[name]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        print(json.dumps(line), flush=True)
         return
     from workloads import CONFIGS
     cfg = CONFIGS[args.workload]
@@ -477,11 +628,12 @@ def main():
             line["cpu_baseline"] = base
             if para:
                 line["cpu_baseline_paradiag_ii"] = para
-    if not args.skip_paradiag_i:
-        print("[bench] ParaDiag-I leg (hybrid wave, 511^2 x 512)", file=sys.stderr, flush=True)
-        line["paradiag_i"] = run_paradiag_i(args, torch)
-        print(f"[bench] ParaDiag-I: {line['paradiag_i']['ms_per_step']:.3f} ms/solve error vs exact "
-              f"{line['paradiag_i']['error_vs_exact']:.3e}", file=sys.stderr, flush=True)
+    for name in legs:
+        print(f"[bench] leg {name}", file=sys.stderr, flush=True)
+        line[name] = EXTRA_LEGS[name](args, torch)
+        print(f"[bench] {name}: {line[name]['ms_per_step']:.3f} ms/step, dominant "
+              f"{line[name]['roofline']['kernel']} at {line[name]['roofline']['frac']:.3f} of its peak",
+              file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -335,7 +335,9 @@ enum {
   PD_STAGE_DOT = 6,        /* Krylov multi-dot products */
   PD_STAGE_UPDATE = 7,     /* Krylov vector updates (fused with the next dots) */
   PD_STAGE_OTHER = 8,      /* reductions of partial sums, solution update, copies */
-  PD_NUM_STAGES = 9
+  PD_STAGE_FINE = 9,       /* parareal: the J fine steps of every coarse interval */
+  PD_STAGE_REACTION = 10,  /* nonlinear solve: reaction term, residual norm, mean slope */
+  PD_NUM_STAGES = 11
 };
 paradiag_status paradiag_set_timing(paradiag_plan plan, int32_t enable);
 paradiag_status paradiag_get_stage_times(paradiag_plan plan, double* ms, int64_t* counts,

@@ -26,7 +26,7 @@ SCHEMES = {"be": 0, "tr": 1, "lf": 2, "hyb": 3, "hyb2": 4}
 PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2, "fp32_bf16x1": 3}
 MODES = {"fgmres": 0, "stationary": 1, "direct": 2, "parareal": 3, "nonlinear": 4}
 STAGES = ["fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv", "matvec", "dot", "update",
-          "other"]
+          "other", "fine", "reaction"]
 
 
 class Problem(ctypes.Structure):

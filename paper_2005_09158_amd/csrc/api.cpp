@@ -409,6 +409,7 @@ static double fft_flops(const Plan& pl) {
 }
 static double time_flops(const Plan& pl) {
   if (pl.hybrid) return 2.0 * pl.g.nt * (double)pl.g.NA;   // two dense nt x nt products per point
+  if (pl.oc) return 2.0 * 2.0 * pl.oc_fh * (double)pl.g.NA;   // (2 Fh) x nt products, both fields
   return fft_flops(pl);
 }
 static double xform_flops(const Plan& pl) {
@@ -430,16 +431,12 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   const SpaceOp& op = pl.op[variant];
   void* const spec_a = buf_a ? buf_a : pl.spec_a;
   void* const spec_b = buf_b ? buf_b : pl.spec_b;
-  if (pl.oc) {
-    Timed t(pl, PD_STAGE_LINE_SOLVE, s, 8.0 * pl.g.NA * (accumulate ? 3.0 : 2.0), 0.0);
-    oc_apply_prec(pl, in, bscale, out, out_f32, accumulate, spec_a, spec_b, s);
-    return;
-  }
   const double vin = 8.0 * pl.g.NA, sb = spec_bytes(pl);
   const double vout = (out_f32 ? 4.0 : 8.0) * pl.g.NA * (accumulate ? 2.0 : 1.0);
   {
     Timed t(pl, PD_STAGE_FFT_FWD, s, vin + sb, time_flops(pl));
-    if (pl.hybrid) time_transform(pl, true, in, spec_a, false, 0, s);
+    if (pl.oc) oc_time_forward(pl, in, bscale, spec_a, spec_b, s);
+    else if (pl.hybrid) time_transform(pl, true, in, spec_a, false, 0, s);
     else fft_time_forward(pl, in, bscale, bstride, spec_a, variant, s);
   }
   if (pl.p.dim == 2) {
@@ -456,7 +453,8 @@ static void apply_prec(Plan& pl, int variant, const double* in, const double* bs
   }
   {
     Timed t(pl, PD_STAGE_FFT_INV, s, sb + vout, time_flops(pl));
-    if (pl.hybrid) time_transform(pl, false, spec_a, out, out_f32, accumulate, s);
+    if (pl.oc) oc_time_inverse(pl, spec_a, out, out_f32, accumulate, spec_b, s);
+    else if (pl.hybrid) time_transform(pl, false, spec_a, out, out_f32, accumulate, s);
     else fft_time_inverse(pl, spec_a, out, out_f32, accumulate, variant, s);
   }
 }
@@ -1344,7 +1342,12 @@ paradiag_status paradiag_parareal(paradiag_plan plan, const double* U0, int32_t 
   bool conv = false;
   while (iters < o->max_iter) {
     copy_vec(u, uprev, g.NA, s);
-    parareal_fine(*pl, U0, uprev, bvec, J, pl->p.alpha, s);
+    {
+      // J tridiagonal solves per interval: 8 flops per row (Thomas elimination
+      // and substitution) plus 3 for the right-hand side; uprev read, b written
+      Timed t(*pl, PD_STAGE_FINE, s, 2.0 * nb, 11.0 * J * (double)g.NA);
+      parareal_fine(*pl, U0, uprev, bvec, J, pl->p.alpha, s);
+    }
     apply_prec(*pl, 0, bvec, nullptr, 0, u, false, 0, s);
     diff_norms(*pl, u, uprev, sm.partial, chunks, s);
     timed_reduce(*pl, sm.partial, 2, nullptr, 0, sm.nrm, nullptr, s, chunks, pl->pin);
@@ -1454,7 +1457,10 @@ paradiag_status paradiag_nonlinear_solve(paradiag_plan plan, const paradiag_cubi
     bool conv = false;
     for (int it = 0;; ++it) {
       apply_A(*pl, 0, uw, false, bvec, r, s);          // r = b - (B1 (x) I + B2 (x) K) u
-      nl_residual(*pl, uw, r, gk, sm.partial, chunks, s);
+      {
+        Timed t(*pl, PD_STAGE_REACTION, s, 3.0 * nb, 8.0 * (double)g.NA);
+        nl_residual(*pl, uw, r, gk, sm.partial, chunks, s);
+      }
       timed_reduce(*pl, sm.partial, 2, nullptr, 0, sm.nrm, nullptr, s, chunks, pl->pin);
       if ((st = wait_host(*pl, s)) != PD_OK) break;
       const double rr = pl->pin[0], gsum = pl->pin[1];

@@ -250,8 +250,13 @@ void matvec_plain(const Plan& pl, const SpaceOp& op, const void* u, bool u_is_f3
 void oc_matvec(const Plan& pl, const void* u, bool u_is_f32, const double* b, double* y, hipStream_t s,
                const double* Vk, int64_t vstride, int nv, double* partial, int sq, const double* V0,
                int v0sq);
-void oc_apply_prec(const Plan& pl, const double* in, const double* scale, void* out, bool out_f32,
-                   int accumulate, void* sa, void* sb, hipStream_t s);
+// Step-(a) of the optimal-control preconditioner: DFT of both fields into
+// tmp, then the 2 x 2 mixing into out (the spectral layout Step-(b) reads)
+void oc_time_forward(const Plan& pl, const double* in, const double* scale, void* out, void* tmp,
+                     hipStream_t s);
+// Step-(c): the unmixing into tmp, then the inverse DFT of both fields into out
+void oc_time_inverse(const Plan& pl, const void* in, void* out, bool out_f32, int accumulate, void* tmp,
+                     hipStream_t s);
 void oc_build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, const double* gsrc,
                   double* b, hipStream_t s);
 // h[b][i] = t s, coef[b][i] = t s^2 with t the reduced dot and s = sigma[b][i]

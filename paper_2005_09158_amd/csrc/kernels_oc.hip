@@ -17,9 +17,10 @@
 // So P^{-1} r: time DFT of both fields (dense product on MFMA: Nt is not a
 // power of two here, since C2 is singular when 4 divides Nt), the mixing
 // c1 = (R1 + i conj(E) R2)/2, c2 = (R1 - i conj(E) R2)/2 into 2 Fh spectral
-// slices, Step-(b) (x-transform, line solves with lambda1 = Sigma, lambda2 =
-// dt^2/2, x-transform back), the unmixing S1 = (y1 + y2)/d2,
-// S2 = i E (y2 - y1)/conj(d2), and the inverse DFT of both fields.
+// slices (oc_time_forward), the plan's Step-(b) (x-transform, line solves with
+// lambda1 = Sigma, lambda2 = dt^2/2, x-transform back), the unmixing
+// S1 = (y1 + y2)/d2, S2 = i E (y2 - y1)/conj(d2), and the inverse DFT of both
+// fields (oc_time_inverse).
 
 #include "internal.h"
 
@@ -140,32 +141,29 @@ void oc_matvec(const Plan& pl, const void* u, bool u_is_f32, const double* b, do
   }
 }
 
-void oc_apply_prec(const Plan& pl, const double* in, const double* scale, void* out, bool out_f32,
-                   int accumulate, void* sa, void* sb, hipStream_t s) {
+void oc_time_forward(const Plan& pl, const double* in, const double* scale, void* out, void* tmp,
+                     hipStream_t s) {
   const Geom& g = pl.g;
-  const int Fh = pl.oc_fh, nt = g.nt;
+  const int Fh = pl.oc_fh;
   const bool f32 = pl.prec != Prec::F64;
-  const SpaceOp& op = pl.op[0];
-  // time DFT of both fields: sa = [2][Fh][...]
-  time_gemm(pl, true, pl.d_wf, in, sa, f32, false, 0, 2, nt, Fh, 2 * Fh, nt, s, scale);
+  // time DFT of both fields: tmp = [2][Fh][...]
+  time_gemm(pl, true, pl.d_wf, in, tmp, f32, false, 0, 2, g.nt, Fh, 2 * Fh, g.nt, s, scale);
   const int64_t n = (int64_t)Fh * g.S;
-  const double2* cE = pl.d_ocmix;
-  if (f32) k_oc_mix<float><<<blocks(n), NT, 0, s>>>((const float*)sa, (float*)sb, cE, Fh, g.S, g.sx);
-  else k_oc_mix<double><<<blocks(n), NT, 0, s>>>((const double*)sa, (double*)sb, cE, Fh, g.S, g.sx);
-  // Step-(b) over the 2 Fh slices (Sigma1 block, then Sigma2 block)
-  void* res = sb;
-  if (pl.p.dim == 2) {
-    xform(pl, op, true, sb, sa, s);
-    line_solve(pl, op, sa, s);
-    xform(pl, op, false, sa, sb, s);
-  } else {
-    line_solve(pl, op, sb, s);
-  }
+  if (f32) k_oc_mix<float><<<blocks(n), NT, 0, s>>>((const float*)tmp, (float*)out, pl.d_ocmix, Fh, g.S, g.sx);
+  else k_oc_mix<double><<<blocks(n), NT, 0, s>>>((const double*)tmp, (double*)out, pl.d_ocmix, Fh, g.S, g.sx);
+}
+
+void oc_time_inverse(const Plan& pl, const void* in, void* out, bool out_f32, int accumulate, void* tmp,
+                     hipStream_t s) {
+  const Geom& g = pl.g;
+  const int Fh = pl.oc_fh;
+  const bool f32 = pl.prec != Prec::F64;
+  const int64_t n = (int64_t)Fh * g.S;
   const double2* c1t = pl.d_ocmix + Fh;
   const double2* c2t = pl.d_ocmix + 2 * Fh;
-  if (f32) k_oc_unmix<float><<<blocks(n), NT, 0, s>>>((const float*)res, (float*)sa, c1t, c2t, Fh, g.S, g.sx);
-  else k_oc_unmix<double><<<blocks(n), NT, 0, s>>>((const double*)res, (double*)sa, c1t, c2t, Fh, g.S, g.sx);
-  time_gemm(pl, false, pl.d_wi, sa, out, f32, out_f32, accumulate, 2, nt, Fh, nt, 2 * Fh, s);
+  if (f32) k_oc_unmix<float><<<blocks(n), NT, 0, s>>>((const float*)in, (float*)tmp, c1t, c2t, Fh, g.S, g.sx);
+  else k_oc_unmix<double><<<blocks(n), NT, 0, s>>>((const double*)in, (double*)tmp, c1t, c2t, Fh, g.S, g.sx);
+  time_gemm(pl, false, pl.d_wi, tmp, out, f32, out_f32, accumulate, 2, g.nt, Fh, g.nt, 2 * Fh, s);
 }
 
 void oc_build_rhs(const Plan& pl, const double* U0, const double* u1, const double* f, const double* gsrc,

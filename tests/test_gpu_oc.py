@@ -85,7 +85,7 @@ def test_oc_fgmres_iterations_table_t2a(n):
     """Iteration counts of Table T2A on the GPU (right-preconditioned flexible
     GMRES, restart 30, true relative residual 1e-7); the oracle's GMRES takes
     the same counts for N <= 64 (tests/test_oracle_ocwave.py), and for N <= 32
-    the GPU solution is compared with the oracle's solve."""
+    the GPU solution is compared with the oracle's."""
     announce(f"oc FGMRES N={n}")
     torch = torch_gpu()
     rows = {r["N"]: r for r in load_golden("table_t2a.json")["rows"]}
@@ -104,8 +104,10 @@ def test_oc_fgmres_iterations_table_t2a(n):
         assert res.converged and res.rel_resid <= 1e-7
         assert abs(res.iters - rows[n][key]) <= 1
         if n <= 32:
-            x = ocwave.solve(p, gamma, b.cpu().numpy().ravel())
-            # the solve error is at most cond(A) times the residual; compare loosely
+            # the oracle's preconditioned GMRES to 1e-11 (equal to its direct
+            # solve, tests/test_oracle_ocwave.py); the GPU solution differs by at
+            # most cond(A) times the 1e-7 residual, so compare loosely
+            x, _, _ = ocwave.gmres(p, gamma, b.cpu().numpy().ravel(), tol=1e-11)
             assert rel_err(u.cpu().numpy().ravel(), x) < 1e-3
         del pd, b, u
         torch.cuda.empty_cache()

@@ -19,4 +19,8 @@ from .fields import (  # noqa: F401
     random_vector,
     hybrid_wave_data,
     hybrid_wave_exact,
+    oc_example_data,
+    oc_example_exact,
+    parareal_initial,
+    nonlinear_initial,
 )

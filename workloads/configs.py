@@ -12,6 +12,15 @@ consumer assembles its own operators from them.
 * ``cfg4``  2D advection-diffusion, 128^2, backward Euler, Nt = 256
             (gradient of a tracking cost through the adjoint solve).
 * ``cfg5``  2D wave equation, 512^2, implicit leap-frog, Nt = 2048, T = 2.
+* ``oc``    optimal control of the 2D wave equation (Section 4's example):
+            255^2 interior points of mesh width 1/256, Nt = 257, T = 2,
+            gamma = 1e-4 (the largest size of Table T2A).
+* ``par``   parareal variant on 1D advection-diffusion (the coefficients of
+            Figure 1.5 on [0, 1]): 1023 points, 64 coarse intervals of
+            dT = 1/16, J = 32 backward Euler fine steps each, alpha = 0.1, a
+            batch of 64 initial states.
+* ``nl``    2D Allen-Cahn u_t = nu Laplacian u + u - u^3, 511^2 points,
+            Nt = 256 backward Euler steps, T = 0.5, alpha = 0.05.
 * ``hyb``   2D wave equation u_tt = Laplacian u + f on the 511^2 interior
             points of mesh width 1/512, T = 2, Nt = 512, hybrid time
             discretisation solved directly (ParaDiag-I; the problem of Table
@@ -44,6 +53,9 @@ class Config:
     seed: int = 0
     with_source: bool = False
     beta: float = 0.0   # control penalty of the tracking cost (cfg4)
+    gamma: float = 0.0  # control penalty of the optimality system (oc)
+    fine_steps: int = 0  # parareal fine steps per coarse interval (par)
+    reaction: tuple = ()  # (k1, k2, k3) of g(u) = k1 u + k2 u^2 + k3 u^3 (nl)
 
     @property
     def dt(self) -> float:
@@ -79,6 +91,12 @@ CONFIGS = {
                    rtol=1e-8, prec="fp32"),
     "hyb": Config("hyb", 2, 511, 511, 512, "hyb2", 2.0, 1.0, 0.0, 0.0, 1.0,
                   rtol=1e-8, prec="fp64", with_source=True),
+    "oc": Config("oc", 2, 255, 255, 257, "lf", 2.0, 1.0, 0.0, 0.0, 1.0,
+                 rtol=1e-7, prec="fp64", with_source=True, gamma=1e-4),
+    "par": Config("par", 1, 1023, 1, 64, "be", 4.0, 0.1, 1.0, 0.0, 0.1,
+                  batch=64, rtol=1e-10, prec="fp64", seed=7, fine_steps=32),
+    "nl": Config("nl", 2, 511, 511, 256, "be", 0.5, 5e-2, 0.0, 0.0, 0.05,
+                 rtol=1e-10, prec="fp64", reaction=(-1.0, 0.0, 1.0)),
 }
 
 

@@ -160,3 +160,44 @@ def hybrid_wave_exact(cfg: Config) -> np.ndarray:
     phi = np.outer(y * (y - 1.0), x * (x - 1.0))
     t = np.arange(1, cfg.nt + 1, dtype=np.float64) * cfg.dt
     return np.sin(2.0 * np.pi * t)[:, None, None] * phi[None]
+
+
+def oc_example_data(cfg: Config):
+    """Data of the optimal-control example of Section 4 on the workload's grid
+    (mesh width 1/(n+1)), whose exact solution is u = e^t S, p = (t - T)^2 S
+    with S = sin(pi x) sin(pi y):
+    f = ((1 + 2 pi^2) e^t - (t - T)^2 / gamma) S and
+    g = (e^t + 2 + 2 pi^2 (t - T)^2) S at t_0 .. t_nt.
+    Returns (U0 [ny][nx], u1 [ny][nx], f [nt+1][ny][nx], g [nt+1][ny][nx])."""
+    x, y = _grids(cfg)
+    S = np.outer(np.sin(np.pi * y), np.sin(np.pi * x))
+    t = np.arange(cfg.nt + 1, dtype=np.float64) * cfg.dt
+    fa = (1.0 + 2.0 * np.pi ** 2) * np.exp(t) - (t - cfg.T) ** 2 / cfg.gamma
+    ga = np.exp(t) + 2.0 + 2.0 * np.pi ** 2 * (t - cfg.T) ** 2
+    return S.copy(), S.copy(), fa[:, None, None] * S[None], ga[:, None, None] * S[None]
+
+
+def oc_example_exact(cfg: Config):
+    """Exact (u at t_1 .. t_nt, p at t_0 .. t_{nt-1}) of the example, each [nt][ny][nx]."""
+    x, y = _grids(cfg)
+    S = np.outer(np.sin(np.pi * y), np.sin(np.pi * x))
+    t = np.arange(cfg.nt + 1, dtype=np.float64) * cfg.dt
+    return np.exp(t[1:])[:, None, None] * S[None], ((t[:-1] - cfg.T) ** 2)[:, None, None] * S[None]
+
+
+def parareal_initial(cfg: Config) -> np.ndarray:
+    """Initial states of the parareal workload, [batch][nx]: a Gaussian bump at
+    a random centre plus 0.1 N(0,1) noise, one per batch entry."""
+    x, _ = _grids(cfg)
+    rng = np.random.default_rng(cfg.seed)
+    c = rng.uniform(0.3, 0.7, cfg.batch)
+    return np.exp(-30.0 * (x[None, :] - c[:, None]) ** 2) + 0.1 * rng.standard_normal((cfg.batch, cfg.nx))
+
+
+def nonlinear_initial(cfg: Config) -> np.ndarray:
+    """Initial state of the Allen-Cahn workload, [ny][nx]: 0.9 sin(pi x) sin(pi y)
+    + 0.2 sin(pi x) sin(2 pi y) plus smooth random modes of amplitude 0.05."""
+    x, y = _grids(cfg)
+    rng = np.random.default_rng(cfg.seed)
+    u = 0.9 * np.outer(np.sin(np.pi * y), np.sin(np.pi * x)) + 0.2 * np.outer(np.sin(2 * np.pi * y), np.sin(np.pi * x))
+    return u + 0.05 * _smooth_modes(rng, 4, x, y, lambda k, l: 1.0 / (k * k + l * l), 2)
