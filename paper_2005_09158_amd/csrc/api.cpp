@@ -306,6 +306,7 @@ size_t tables_bytes(const Plan& pl) {
       b += 2 * align_up(gemm_matrix_bytes(pl.prec, gm));              // g_fwd, g_inv
       if (pl.schur) b += align_up(2 * n * n * spec_elem_bytes(pl.prec));  // T (line precision)
       if (pl.schur) b += align_up((size_t)2 * g.F * n * g.sy * spec_elem_bytes(pl.prec));  // line LU
+      if (sweep_windowed(pl)) b += align_up((size_t)3 * 4 * n * n * 2);   // far-coupling B^T, bf16 parts
     }
   }
   b += 2 * align_up((size_t)g.spec_elems * spec_elem_bytes(pl.prec));
@@ -1196,7 +1197,36 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
         if (pl->prec == Prec::F64) store_compute<double>((void*)op.tup, tp, s, keep);
         else store_compute<float>((void*)op.tup, tp, s, keep);
         op.lu = take((size_t)2 * g.F * n * g.sy * spec_elem_bytes(pl->prec));
+        op.tfar = nullptr;
+        if (sweep_windowed(*pl)) {
+          // the windowed sweep's far-coupling product: B^T[m][k] with m < n the
+          // real and m >= n the imaginary part of mode q = m mod n, and k < n
+          // the real, k >= n the imaginary part of the solved mode:
+          // [[Tr, -Ti], [Ti, Tr]] row-wise; three bf16 parts (hi, mid, lo)
+          const size_t n2 = 2 * (size_t)n;
+          std::vector<double> part[3];
+          for (auto& v : part) v.assign(n2 * n2, 0.0);
+          for (int q = 0; q < n; ++q)
+            for (int j = 0; j < n; ++j) {
+              const cd t = op.Tm[(size_t)q * n + j];
+              const double e[4] = {t.real(), -t.imag(), t.imag(), t.real()};
+              const size_t at[4] = {q * n2 + j, q * n2 + n + j, (n + q) * n2 + j, (n + q) * n2 + n + j};
+              for (int c = 0; c < 4; ++c) {
+                float rest = (float)e[c];
+                for (int a = 0; a < 3; ++a) {
+                  uint32_t u = (uint32_t)to_bf16_bits(rest) << 16;
+                  float h;
+                  std::memcpy(&h, &u, 4);
+                  part[a][at[c]] = h;
+                  rest -= h;
+                }
+              }
+            }
+          op.tfar = take(3 * n2 * n2 * 2);
+          for (int a = 0; a < 3; ++a) store_compute<Bf16Bits>((char*)op.tfar + 2 * a * n2 * n2, part[a], s, keep);
+        }
       } else {
+        op.tfar = nullptr;
         op.tup = nullptr;
         op.lu = nullptr;
       }

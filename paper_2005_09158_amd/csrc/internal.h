@@ -102,6 +102,9 @@ struct SpaceOp {
   const void* g_inv = nullptr;  // W -> W * Q^T
   const void* tup = nullptr;    // Schur T (planar re/im, [2][nx][nx], compute format); null if diagonal
   void* lu = nullptr;           // Schur path: inverse LU pivots of every line, [F][nx][ny] complex
+  // windowed back-sweep: the real block form of T for the far-coupling product,
+  // as three bf16 parts (hi, mid, lo), [3][2 nx][2 nx] (see sweep_windowed)
+  const void* tfar = nullptr;
   // host copies
   std::vector<cd> Q, Tm;        // nx*nx complex (row-major): K_x = Q T Q^H
 };
@@ -217,6 +220,10 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
 void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
+// true where the back-sweep runs in windows of SWEEP_WINDOW modes, their
+// coupling to later windows as one split-bf16 MFMA product (op.tfar needed)
+constexpr int SWEEP_WINDOW = 64;
+bool sweep_windowed(const Plan& pl);
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu
 // all-at-once operator
 // y = A u (or b - A u).  With nv > 0 also the partial dots of y with the

@@ -35,6 +35,16 @@ using namespace tri;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) {
+  __bf16 h = (__bf16)v;
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __builtin_bit_cast(float, (unsigned int)b << 16);
+}
 
 template <typename T> struct SweepMfma;
 template <> struct SweepMfma<float> {
@@ -348,6 +358,42 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
   }
 }
 
+// Block k0 .. k0 + nk - 1 of a slice from wave 0's copy of its solution
+// (value i of line q of lane p at (q R + i) 64 + p) to global memory: one
+// thread per row y = p R + i writes that row's nk modes (real, then imaginary
+// parts), 16-byte vectors when VEC and the block is full.
+template <typename T, int NB, int R, bool VEC>
+__device__ __forceinline__ void wsol_store(T* slice, const Cx<T>* wsol, int k0, int nk, int sx, int sy, int P,
+                                           int tid, int nthr) {
+  for (int e = tid; e < P * R; e += nthr) {
+    const int p = e % P, i = e / P, y = p * R + i;
+    if (y >= sy) continue;
+    T re[NB], im[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const Cx<T> v = wsol[(q * R + i) * 64 + p];
+      re[q] = v.x;
+      im[q] = v.y;
+    }
+    T* row = slice + (int64_t)y * 2 * sx + k0;
+    if (VEC && nk == NB && sizeof(T) == 4 && NB % 4 == 0) {
+      typedef T V4T __attribute__((ext_vector_type(4)));
+#pragma unroll
+      for (int h = 0; h < NB / 4; ++h) {
+        *reinterpret_cast<V4T*>(row + 4 * h) = V4T{re[4 * h], re[4 * h + 1], re[4 * h + 2], re[4 * h + 3]};
+        *reinterpret_cast<V4T*>(row + sx + 4 * h) = V4T{im[4 * h], im[4 * h + 1], im[4 * h + 2], im[4 * h + 3]};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < nk) {
+          row[q] = re[q];
+          row[sx + q] = im[q];
+        }
+    }
+  }
+}
+
 // Pipelined back-sweep: one workgroup of 1 + NCW waves per (right-hand side,
 // frequency) slice; blocks of NB modes from the last to the first.  Step b:
 //   * all waves write block b+1 (solved in the previous step) from LDS to
@@ -371,17 +417,18 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
 constexpr int NCW = 3;
 constexpr int SWT = 64 * (NCW + 1);
 
-template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B>
+template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B, bool WIN>
 __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                      const T* __restrict__ tup, const T* __restrict__ lu,
-                                                     double lo, double up, int F, int sx, int sy, int ldy) {
+                                                     double lo, double up, int F, int sx, int sy, int ldy,
+                                                     int klo, int khi) {
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
   using MF = SweepMfma<T>;
   constexpr int NCB = 2 * NB / 16;
   extern __shared__ __align__(16) unsigned char smraw[];
   T* tiles = reinterpret_cast<T*>(smraw);       // [2 buffers][re, im][NB][ldy]
   const int TS = 2 * NB * ldy;
-  T* tbs = tiles + 2 * TS;                      // [2][NB][NB] complex: lambda2 T_{q' q} inside the block, q' < q
+  T* tbs = tiles + (WIN ? 1 : 2) * TS;          // [2][NB][NB] complex: lambda2 T_{q' q} inside the block, q' < q
   T* tns = tbs + 4 * NB * NB;                   // [2][NB][NB] complex: lambda2 T_{q j} towards the block after
   // wave 0's copy of the block it solved last: value i of line q of lane l at
   // (q R + i) 64 + l (conflict-free), read back by the next step's near coupling
@@ -421,7 +468,10 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
   const double2 l2 = lam[F + n];
   const T l2r = (T)l2.x, l2i = (T)l2.y;
   const int wave = threadIdx.x >> 6;
-  const int nblk = (sx + NB - 1) / NB;
+  // the window of modes [klo, khi) (klo a multiple of NB; khi one too, or sx):
+  // blocks blo .. bhi-1; modes from khi on are already folded into the tiles
+  const int blo = klo / NB, bhi = (khi + NB - 1) / NB;
+  const int nblk = bhi - blo;
   // Far couplings come in pairs of blocks: in a step with far set, the rows a
   // wave prepares get their coupling to every mode beyond block kb for blocks
   // kb-1 and kb-2 in one pass over those modes (each W fragment read once,
@@ -455,8 +505,8 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
   };
 
   const T* lun = lu + (int64_t)n * sx * sy * 2;
-  {  // prologue: the last block (the only one that may be partial)
-    const int k0 = (nblk - 1) * NB, nk = sx - k0;
+  {  // prologue: the last block of the window (the only one that may be partial)
+    const int k0 = (bhi - 1) * NB, nk = khi - k0;
     tile_load_by(slice, tiles, tiles + NB * ldy, k0, nk, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
     stage_coef(tbs, k0, k0, nk, true, (int)threadIdx.x, SWT);
     if constexpr (PIVL)
@@ -476,21 +526,40 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int cur = st & 1, nxt = cur ^ 1;
-    const int kb = nblk - 1 - st, k0 = kb * NB, nk = min(NB, sx - k0), kend = k0 + nk;
-    T* cre = tiles + cur * TS;
+    // tiles: double-buffered, or in a window one buffer (wave 0 takes block kb
+    // into registers before the coupling waves stage block kb-1 over it)
+    const int tcur = WIN ? 0 : cur, tnxt = WIN ? 0 : nxt;
+    const int kb = bhi - 1 - st, k0 = kb * NB, nk = min(NB, khi - k0), kend = k0 + nk;
+    T* cre = tiles + tcur * TS;
     T* cim = cre + NB * ldy;
-    T* nre = tiles + nxt * TS;
+    T* nre = tiles + tnxt * TS;
     T* nim = nre + NB * ldy;
     if (st > 0) {   // block kb+1, solved in the previous step, to global memory
-      const int k0p = k0 + NB, nkp = min(NB, sx - k0p);
-      if (VEC && nkp == NB) tile_store_vec<T, NB, R * P>(slice, nre, nim, k0p, sx, sy, ldy, R, tid, SWT);
+      const int k0p = k0 + NB, nkp = min(NB, khi - k0p);
+      if constexpr (WIN) wsol_store<T, NB, R, VEC>(slice, wsol, k0p, nkp, sx, sy, P, tid, SWT);
+      else if (VEC && nkp == NB) tile_store_vec<T, NB, R * P>(slice, nre, nim, k0p, sx, sy, ldy, R, tid, SWT);
       else tile_store_by(slice, nre, nim, k0p, nkp, NB, sx, sy, ldy, R, tid, SWT);
       // block kb's pivots, loaded by the coupling waves in the previous step
       if (PIVL && tid >= 64) piv_store(tid - 64, 2 * NB * sy / PVW);
     }
     __syncthreads();   // block kb+1 in global memory; its LDS buffer is free; block kb's pivots staged
-    const int k0n = k0 - NB;   // next block (always full) when kb > 0
-    const bool far = ((st + phase) & 1) == 0;
+    // wave 0: block kb (carrying its coupling to every mode beyond block kb+1)
+    // into registers
+    Cx<T> d[NB][R];
+    if (wave == 0) {
+      const int p = lane % P;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int idx = q * ldy + p * (R + 1) + i;
+          d[q][i] = (lane < P && q < nk) ? Cx<T>{cre[idx], cim[idx]} : cz<T>();
+        }
+    }
+    if constexpr (WIN) __syncthreads();   // the single tile buffer is free for block kb-1
+    const int k0n = k0 - NB;   // next block (always full) when kb > blo
+    // windowed: no pairing, every step couples block kb-1 to the rest of the window
+    const bool far = WIN || ((st + phase) & 1) == 0;
     // Rows [y0, y1) of block kb-1: staged into the LDS buffer, coupled to every
     // mode beyond block kb (read from global memory), and lambda2 times the
     // coupling subtracted.  One wave; it touches only its own rows.
@@ -498,7 +567,22 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       constexpr int RBX = decltype(rbx)::value;
       tile_rows_load<T, NB, RBX * 16, VEC>(slice, nre, nim, k0n, sx, y0, y1, ldy, R, lane);
       typename MF::acc_t acc[RBX][NCB];
-      if (far) {   // blocks kb-1 and kb-2 against every mode beyond block kb
+      if constexpr (WIN) {   // block kb-1 against the window's modes beyond block kb
+        typename MF::acc_t a1[1][RBX][NCB];
+#pragma unroll
+        for (int i = 0; i < RBX; ++i)
+#pragma unroll
+          for (int j = 0; j < NCB; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a1[0][i][j][v] = 0;
+        const int k0t[1] = {k0n};
+        const bool tok[1] = {true};
+        coupling_far<T, NB, RBX, 1, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, khi, y0, lr, lk, a1);
+#pragma unroll
+        for (int i = 0; i < RBX; ++i)
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) acc[i][j] = a1[0][i][j];
+      } else if (far) {   // blocks kb-1 and kb-2 against every mode beyond block kb
         typename MF::acc_t a2[2][RBX][NCB];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -509,8 +593,8 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
 #pragma unroll
               for (int v = 0; v < 4; ++v) a2[h][i][j][v] = 0;
         const int k0t[2] = {k0n, k0n - NB};
-        const bool tok[2] = {true, k0n >= NB};
-        coupling_far<T, NB, RBX, 2, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, sx, y0, lr, lk, a2);
+        const bool tok[2] = {true, k0n - NB >= klo};
+        coupling_far<T, NB, RBX, 2, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, khi, y0, lr, lk, a2);
 #pragma unroll
         for (int i = 0; i < RBX; ++i)
 #pragma unroll
@@ -526,7 +610,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
           for (int j = 0; j < NCB; ++j) a1[0][i][j] = carry[i][j];
         const int k0t[1] = {k0n};
         const bool tok[1] = {true};
-        coupling_far<T, NB, RBX, 1, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, min(kend + NB, sx), y0,
+        coupling_far<T, NB, RBX, 1, VEC>(slice, tre, tim, sx, sy, k0t, tok, kend, min(kend + NB, khi), y0,
                                          lr, lk, a1);
 #pragma unroll
         for (int i = 0; i < RBX; ++i)
@@ -543,8 +627,8 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
         for (int v = 0; v < 4; ++v) {
           const int y = y0 + i * 16 + MF::row(lk, v);
           const int idx = lidx(lr, y, ldy, R);
-          tr_[i][v] = (y < sy && col_ok) ? nre[idx] : (T)0;
-          ti_[i][v] = (y < sy && col_ok) ? nim[idx] : (T)0;
+          tr_[i][v] = (y < y1 && col_ok) ? nre[idx] : (T)0;   // y1 <= sy: this call's rows only
+          ti_[i][v] = (y < y1 && col_ok) ? nim[idx] : (T)0;
         }
 #pragma unroll
       for (int i = 0; i < RBX; ++i)
@@ -559,7 +643,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
             cr = acc[i][0][v];
             ci = dpp_mov<0x108>(acc[i][0][v]);   // imaginary part from lane lr + 8 (row_shl:8)
           }
-          if (y < sy && col_ok) {
+          if (y < y1 && col_ok) {
             const int idx = lidx(lr, y, ldy, R);
             nre[idx] = tr_[i][v] - (l2r * cr - l2i * ci);
             nim[idx] = ti_[i][v] - (l2r * ci + l2i * cr);
@@ -606,14 +690,6 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
             iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
         }
       };
-      Cx<T> d[NB][R];
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int idx = q * ldy + p * (R + 1) + i;
-          d[q][i] = (active && q < nk) ? Cx<T>{cre[idx], cim[idx]} : cz<T>();
-        }
       Cx<T> ivn[R];
       load_inv(nk - 1, ivn);
 #pragma unroll
@@ -656,7 +732,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
         for (int i = 0; i < R; ++i) {
           wsol[(q * R + i) * 64 + lane] = (q < nk) ? d[q][i] : cz<T>();
           const int idx = q * ldy + p * (R + 1) + i;
-          if (active && q < nk) {
+          if (!WIN && active && q < nk) {
             cre[idx] = d[q][i].x;
             cim[idx] = d[q][i].y;
           }
@@ -664,8 +740,8 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
       // the first W0B row blocks of block kb-1's preparation: wave 0 finishes
       // its lines before the coupling waves finish theirs, so it takes a share
       if constexpr (W0B > 0)
-        if (kb > 0) prep_rows(std::integral_constant<int, W0B>{}, 0, min(sy, W0B * 16), lane, lr, lk);
-    } else if (kb > 0) {
+        if (kb > blo) prep_rows(std::integral_constant<int, W0B>{}, 0, min(sy, W0B * 16), lane, lr, lk);
+    } else if (kb > blo) {
       // ---- block kb-1: tile, coupling to the modes beyond block kb -----
       // Wave cw stages exactly the rows its accumulators cover, so its
       // subtraction depends only on its own LDS writes (in program order).
@@ -696,7 +772,12 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
           cni = tim[row + k0 + qb];
         }
       }
-      prep_rows(std::integral_constant<int, RB>{}, y0, y1, lane, lr, lk);
+      if constexpr (WIN) {   // passes of 32 rows: registers for two workgroups per CU
+        for (int yy = y0; yy < y1; yy += 32)
+          prep_rows(std::integral_constant<int, 2>{}, yy, min(y1, yy + 32), lane, lr, lk);
+      } else {
+        prep_rows(std::integral_constant<int, RB>{}, y0, y1, lane, lr, lk);
+      }
       if (ct < NB * NB) {
         T* bt = tbs + nxt * 2 * NB * NB;
         T* bn = tns + nxt * 2 * NB * NB;
@@ -708,10 +789,14 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
     __syncthreads();   // block kb solved (LDS buffer cur); block kb-1 staged
   }
-  {  // the first block, solved in the last step
-    const int nkp = min(NB, sx);
-    T* pre = tiles + ((nblk - 1) & 1) * TS;
-    tile_store_by(slice, pre, pre + NB * ldy, 0, nkp, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
+  {  // the first block of the window, solved in the last step
+    const int nkp = min(NB, khi - klo);
+    if constexpr (WIN) {
+      wsol_store<T, NB, R, VEC>(slice, wsol, klo, nkp, sx, sy, P, (int)threadIdx.x, SWT);
+    } else {
+      T* pre = tiles + ((nblk - 1) & 1) * TS;
+      tile_store_by(slice, pre, pre + NB * ldy, klo, nkp, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
+    }
   }
 }
 
@@ -962,6 +1047,190 @@ __global__ __launch_bounds__(NT) void k_line_lu(T* __restrict__ lu, const double
   }
 }
 
+// Far coupling of one window of the back-sweep, over every slice at once.
+// For the window of modes [klo, klo + NW) and every row (slice, y) of the
+// spectral buffer:
+//
+//   R[row][klo + q] -= lambda2_n sum_{j >= khi} W[row][j] T[klo + q][j],  q < NW,
+//
+// with W the solved modes (already final in the buffer) and khi = klo + NW.
+// In the real block form, row [Wr | Wi] (the buffer's row-planar layout) times
+// B[k][n'] with n' < NW the real and n' >= NW the imaginary part of mode
+// klo + n' mod NW:  B^T = [[Tr, -Ti], [Ti, Tr]] restricted to those rows and to
+// the columns j >= khi of both halves (tfar holds the whole 2nx x 2nx B^T).
+// Operands in split bf16 (three parts each, the six products down to relative
+// size 2^-16, as in the x-transform), float32 accumulation.  Tiles of 128 rows
+// x 2 NW = 128 columns x 32, 2 x 2 waves of 64 x 64; the accumulators go
+// through LDS so that each thread can combine a mode's real and imaginary
+// parts and apply the complex lambda2 of its row's frequency.  Needs
+// nx % 32 == 0 (k chunks do not straddle the two halves; 16-byte loads).
+constexpr int FAR_NW = SWEEP_WINDOW;
+
+__global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, const unsigned short* __restrict__ Bt,
+                                                  const double2* __restrict__ lam, int64_t rows, int F, int sx,
+                                                  int sy, int klo, int khi) {
+  constexpr int BM = 128, BN = 2 * FAR_NW, BK = 32, NA = 3;
+  static_assert(BN == 128, "tile");
+  auto off = [](int r, int ch) { return r * BK + 8 * (ch ^ ((r >> 1) & 3)); };
+  constexpr int STAGE = 2 * NA * BM * BK;      // unsigned shorts of the A and B staging
+  constexpr int LDC = BN + 1;                  // float stride of the accumulator half-tile
+  constexpr int WORDS = (STAGE / 2 > 64 * LDC) ? STAGE / 2 : 64 * LDC;
+  __shared__ __align__(16) float smem[WORDS];
+  unsigned short* As = reinterpret_cast<unsigned short*>(smem);
+  unsigned short* Bs = As + NA * BM * BK;
+  float* Cs = smem;
+
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int L = sx - khi;                      // solved modes beyond the window
+  const int K2 = 2 * L;
+  const int64_t ld = 2 * (int64_t)sx;          // row length of the buffer and of B^T
+  const int64_t part = ld * ld;                // elements per bf16 part of B^T
+
+  // two k chunks in flight in registers (the W rows come from HBM once per
+  // tile, so one chunk of prefetch leaves most of the latency exposed)
+  float4 ra[2][4];
+  uint4 rb[2][NA][2];
+  auto gk = [&](int kk) { return kk < L ? khi + kk : sx + khi + (kk - L); };
+  auto gload = [&](auto bufc, int kk) {
+    constexpr int bb = decltype(bufc)::value;
+    const int k = gk(kk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t gm = m0 + (tid >> 3) + 32 * i;
+      ra[bb][i] = (gm < rows) ? *reinterpret_cast<const float4*>(spec + gm * ld + k + 4 * (tid & 7))
+                              : float4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int nl = (tid >> 2) + 64 * i;      // local column: real parts of the window, then imaginary
+      const int np = nl < FAR_NW ? klo + nl : sx + klo + (nl - FAR_NW);
+      const int64_t o = (int64_t)np * ld + k + 8 * (tid & 3);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) rb[bb][a][i] = *reinterpret_cast<const uint4*>(Bt + a * part + o);
+    }
+  };
+  auto sstore = [&](auto bufc) {
+    constexpr int bb = decltype(bufc)::value;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = (tid >> 3) + 32 * i, c = 4 * (tid & 7);
+      const float v[4] = {ra[bb][i].x, ra[bb][i].y, ra[bb][i].z, ra[bb][i].w};
+      us4 prt[NA];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float rest = v[q];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          prt[a][q] = bf16_bits(rest);
+          if (a + 1 < NA) rest -= bf16_val(prt[a][q]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<us4*>(&As[a * BM * BK + off(r, c >> 3) + (c & 7)]) = prt[a];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a * BN * BK + off(r, c >> 3)]) = rb[bb][a][i];
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&]() {
+    bf8 a[NA][4], b[NA][4];
+#pragma unroll
+    for (int x = 0; x < NA; ++x) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[x][i] = *reinterpret_cast<const bf8*>(&As[x * BM * BK + off(wm0 + 16 * i + lr, lk)]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x * BN * BK + off(wn0 + 16 * j + lr, lk)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+      }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  gload(I0{}, 0);
+  if (BK < K2) gload(I1{}, BK);
+  for (int kk = 0; kk < K2; kk += 2 * BK) {
+    __syncthreads();
+    sstore(I0{});
+    __syncthreads();
+    if (kk + 2 * BK < K2) gload(I0{}, kk + 2 * BK);
+    compute();
+    if (kk + BK >= K2) break;
+    __syncthreads();
+    sstore(I1{});
+    __syncthreads();
+    if (kk + 3 * BK < K2) gload(I1{}, kk + 3 * BK);
+    compute();
+  }
+  // the accumulators through LDS (reusing the staging buffers), 64 rows at a
+  // time: the two waves of row half h write, then every thread takes
+  // R -= lambda2 C for consecutive modes of one row
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if ((wave >> 1) == h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cs[(16 * i + 4 * lk + v) * LDC + wn0 + 16 * j + lr] = acc[i][j][v];
+    __syncthreads();
+    // every global load of the update first (one round trip), then the stores
+    static_assert(FAR_NW == 64, "thread -> (row, mode) map");
+    constexpr int PER = 64 * FAR_NW / NT;
+    const int q = tid & 63;
+    float yr[PER], yi[PER];
+    double2 l2v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int r = (tid >> 6) + 4 * t;
+      const int64_t gm = m0 + 64 * h + r;
+      yr[t] = 0.f;
+      yi[t] = 0.f;
+      l2v[t] = double2{0.0, 0.0};
+      if (gm < rows) {
+        const float* src = spec + gm * ld + klo + q;
+        yr[t] = src[0];
+        yi[t] = src[sx];
+        l2v[t] = lam[F + (int)((gm / sy) % F)];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int r = (tid >> 6) + 4 * t;
+      const int64_t gm = m0 + 64 * h + r;
+      if (gm < rows) {
+        const float l2r = (float)l2v[t].x, l2i = (float)l2v[t].y;
+        const float cr = Cs[r * LDC + q], ci = Cs[r * LDC + FAR_NW + q];
+        float* dst = spec + gm * ld + klo + q;
+        dst[0] = yr[t] - (l2r * cr - l2i * ci);
+        dst[sx] = yi[t] - (l2r * ci + l2i * cr);
+      }
+    }
+  }
+}
+
 struct SweepShape { int R, P, RB, ldy; size_t lds; bool vec; };
 
 template <typename T, int NB, int BK>
@@ -993,27 +1262,33 @@ void launch_one(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
 
 // Pipelined kernel: LDS bytes of two tiles and two coupling blocks.
 template <typename T, int NB>
-size_t piped_lds(const SweepShape& sh) {
+size_t piped_lds(const SweepShape& sh, bool win) {
   // two tiles, two pairs of coefficient blocks, wave 0's solution copy
-  // + the pivots of one block (lines of up to 256 rows)
-  return sizeof(T) * ((size_t)4 * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64 +
+  // + the pivots of one block (lines of up to 256 rows, or in a window)
+  // (a window keeps one tile; its pivots come from LDS only for short lines)
+  return sizeof(T) * ((size_t)(win ? 2 : 4) * NB * sh.ldy + (size_t)8 * NB * NB + (size_t)2 * NB * sh.R * 64 +
                       (sh.R * sh.P <= 256 ? (size_t)2 * NB * sh.R * sh.P : 0));
 }
 
 template <typename T, int R, int P, int NB, int RB, int W0B>
-void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
+void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo, int khi) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, 16>(pl);
-  const size_t lds = piped_lds<T, NB>(sh);
+  const bool win = khi - klo < g.sx;
+  const size_t lds = piped_lds<T, NB>(sh, win);
   // two workgroups per CU where the registers allow (lines of up to 256 rows):
   // an odd number of slices, or more slices than CUs, then leaves no CU idle
   // while a last slice runs alone
   constexpr int MINB = (R == 4) ? 2 : 1;
-  auto kfn = sh.vec ? k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B>
-                    : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B>;
+  // a window's kernel (one tile buffer, no far pairs) fits two workgroups per
+  // CU at every line length
+  auto kfn = sh.vec ? (win ? k_schur_sweep<T, R, P, NB, RB, true, 2, W0B, true>
+                           : k_schur_sweep<T, R, P, NB, RB, true, MINB, W0B, false>)
+                    : (win ? k_schur_sweep<T, R, P, NB, RB, false, 2, W0B, true>
+                           : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B, false>);
   lds_limit((const void*)kfn, lds);
   kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
-                                       g.F, g.sx, g.sy, sh.ldy);
+                                       g.F, g.sx, g.sy, sh.ldy, klo, khi);
 }
 
 // (NB, BK) of the wide kernel per precision and row count.
@@ -1032,17 +1307,18 @@ template <> struct PipedCfg<double> { static constexpr int NB4 = 0, NB8 = 0; };
 // MFMA rate) is the long pole, and there all four waves run it.
 
 template <typename T>
-void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s) {
+void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo = 0, int khi = -1) {
   using C = SweepCfg<T>;
   using PC = PipedCfg<T>;
   SweepShape sh = sweep_shape<T, C::NB, C::BK>(pl);
+  if (khi < 0) khi = pl.g.sx;
   if constexpr (PC::NB8 > 0) {   // float32: pipelined kernel
     // row blocks of 16 rows: W0 for wave 0 (after its lines), RB per coupling
     // wave, W0 + 3 RB >= rows / 16: <= 64 rows: 0 + 3 x 2, <= 128: 0 + 3 x 3,
     // <= 256: 1 + 3 x 5, <= 512: 2 + 3 x 10
 #define PD_PIPED(RR, PP, BB, W0, NBV)                                                     \
   if (sh.R == RR && sh.P == PP) {                                                         \
-    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s);                                \
+    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s, klo, khi);                      \
     return;                                                                               \
   }
     PD_PIPED(4, 1, 2, 0, PC::NB4) PD_PIPED(4, 2, 2, 0, PC::NB4) PD_PIPED(4, 4, 2, 0, PC::NB4)
@@ -1074,7 +1350,8 @@ size_t schur_sweep_lds(const Plan& pl) {
     return a.RB == 8 ? sweep_shape<double, SweepCfg<double>::NB8, SweepCfg<double>::BK8>(pl).lds : a.lds;
   }
   SweepShape a = sweep_shape<float, 16, 32>(pl);
-  return a.R == 4 ? piped_lds<float, PipedCfg<float>::NB4>(a) : piped_lds<float, PipedCfg<float>::NB8>(a);
+  const bool win = sweep_windowed(pl);
+  return a.R == 4 ? piped_lds<float, PipedCfg<float>::NB4>(a, win) : piped_lds<float, PipedCfg<float>::NB8>(a, win);
 }
 
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {
@@ -1087,9 +1364,34 @@ void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {
     k_line_lu<float><<<grid, NT, 0, s>>>((float*)op.lu, pl.d_lam, op.tk, op.lo, op.di, op.up, g.F, g.sx, g.sy);
 }
 
+bool sweep_windowed(const Plan& pl) {
+  const Geom& g = pl.g;
+  return pl.schur && pl.p.dim == 2 && pl.prec == Prec::BF16 && g.sx % SWEEP_WINDOW == 0 &&
+         g.sx >= 2 * SWEEP_WINDOW && g.sx % 32 == 0;
+}
+
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
-  if (pl.prec == Prec::F64) launch<double>(pl, op, (double*)spec, s);
-  else launch<float>(pl, op, (float*)spec, s);
+  if (pl.prec == Prec::F64) {
+    launch<double>(pl, op, (double*)spec, s);
+    return;
+  }
+  if (!sweep_windowed(pl) || !op.tfar) {
+    launch<float>(pl, op, (float*)spec, s);
+    return;
+  }
+  // windows from the last modes to the first: fold the coupling to every
+  // later window into the tiles with one product over all slices, then sweep
+  // the window's modes
+  const Geom& g = pl.g;
+  const int64_t rows = (int64_t)g.B * g.F * g.sy;
+  const unsigned tiles = (unsigned)((rows + 127) / 128);
+  for (int khi = g.sx; khi > 0; khi -= SWEEP_WINDOW) {
+    const int klo = khi - SWEEP_WINDOW;
+    if (khi < g.sx)
+      k_sweep_far<<<tiles, NT, 0, s>>>((float*)spec, (const unsigned short*)op.tfar, pl.d_lam, rows, g.F,
+                                       g.sx, g.sy, klo, khi);
+    launch<float>(pl, op, (float*)spec, s, klo, khi);
+  }
 }
 
 }  // namespace pd

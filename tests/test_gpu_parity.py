@@ -93,6 +93,33 @@ def test_schur_sweep_shapes(nx, ny, prec):
     assert err < PREC_TOL[prec]
 
 
+# Windowed back-sweep (split bf16, x-sizes that are multiples of 64): the
+# coupling of each 64-mode window to the later ones is one product over all
+# slices before the window is swept.  Rows per line from 20 to 300 (1 .. 64
+# lanes; 150 and 256 rows give the coupling waves row ranges that are not a
+# multiple of their 32-row passes), two to four windows.  The error against
+# the oracle must stay at the float32 level of the same plan in plain float32
+# (whose sweep is not windowed): within 4x of it, plus 1e-6.
+WINDOW_SHAPES = [(128, 20), (192, 37), (256, 64), (192, 150), (128, 256), (128, 300)]
+
+
+@pytest.mark.parametrize("nx,ny", WINDOW_SHAPES)
+def test_windowed_sweep_shapes(nx, ny):
+    announce(f"windowed sweep {nx}x{ny}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nt=8, scheme="tr", T=0.5, nu=0.05, ax=1.0, ay=0.5, alpha=1e-2)
+    r = np.random.default_rng(11).standard_normal((cfg["nt"], nx * ny))
+    errs = {}
+    for prec in ("fp32", "fp32_bf16gemm"):
+        torch, pd, prob = make(cfg, prec)
+        z = pd.apply_precond(to_gpu(torch, r, pd.shape))
+        torch.cuda.synchronize()
+        if prec == "fp32":
+            z_ref = o_prec.three_steps(prob, r)
+        errs[prec] = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
+    print(f"  rel err fp32 {errs['fp32']:.3e}, windowed split bf16 {errs['fp32_bf16gemm']:.3e}")
+    assert errs["fp32_bf16gemm"] <= 4 * errs["fp32"] + 1e-6
+
+
 # Line-solver shapes (sine basis): lines of 256 .. 512 rows take 8 rows per
 # lane (32 or 64 lanes per line), 1024 and 2048 rows take 16 and 32 rows per
 # lane (tiles of 4 modes; 135 KiB of LDS at 2048 rows in float64), a ragged
