@@ -30,6 +30,8 @@
 // for the float32 and bf16 instructions and C[l / 16 + 4 v][l % 16] for the
 // float64 one (checked on gfx950 with a single-wave product).
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace pd {
@@ -200,7 +202,7 @@ __device__ __forceinline__ float bf16_val(unsigned short b) {
 }
 
 template <int SPLIT>
-__global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
+__global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A,
                                                   const unsigned short* __restrict__ Bt,
                                                   float* __restrict__ C, int64_t M, int N, int K,
                                                   int ntn, int64_t nblocks) {
@@ -227,30 +229,46 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
   const int64_t NKp = (int64_t)N * K;   // elements per bf16 part of the matrix
 
   // per-thread staging: A 4 x float4 (rows tid/8 + 32 i, k = 4 (tid%8)),
-  // B 2 x 16 bytes per part (rows tid/4 + 64 i, k = 8 (tid%4))
-  float4 ra[4];
+  // B 2 x 16 bytes per part (rows tid/4 + 64 i, k = 8 (tid%4)).  Rows beyond
+  // M or N load a valid row and are zeroed afterwards, so the loads carry no
+  // branches and the waits can count them.
+  float4 ra[1][4];
   uint4 rb[NA][2];
-  auto gload = [&](int k0) {
+  int64_t arow[4];
+  bool aok[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int64_t gm = m0 + (tid >> 3) + 32 * i;
-      ra[i] = (gm < M) ? *reinterpret_cast<const float4*>(A + gm * K + k0 + 4 * (tid & 7))
-                       : float4{0.f, 0.f, 0.f, 0.f};
-    }
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gm = m0 + (tid >> 3) + 32 * i;
+    aok[i] = gm < M;
+    arow[i] = (aok[i] ? gm : M - 1) * K + 4 * (tid & 7);
+  }
+  int64_t brow[2];
+  bool bok[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      int gn = n0 + (tid >> 2) + 64 * i;
-      int64_t off = (int64_t)gn * K + k0 + 8 * (tid & 3);
+  for (int i = 0; i < 2; ++i) {
+    const int gn = n0 + (tid >> 2) + 64 * i;
+    bok[i] = gn < N;
+    brow[i] = (int64_t)(bok[i] ? gn : N - 1) * K + 8 * (tid & 3);
+  }
+  // the next k tile is loaded while the current one is multiplied
+  auto aload = [&](auto bufc, int k0) {
+    constexpr int bb = decltype(bufc)::value;
 #pragma unroll
-      for (int a = 0; a < NA; ++a)
-        rb[a][i] = (gn < N) ? *reinterpret_cast<const uint4*>(Bt + a * NKp + off) : uint4{0, 0, 0, 0};
-    }
+    for (int i = 0; i < 4; ++i) ra[bb][i] = *reinterpret_cast<const float4*>(A + arow[i] + k0);
   };
-  auto sstore = [&]() {
+  auto bload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) rb[a][i] = *reinterpret_cast<const uint4*>(Bt + a * NKp + brow[i] + k0);
+  };
+  auto sstore = [&](auto bufc) {
+    constexpr int bb = decltype(bufc)::value;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int r = (tid >> 3) + 32 * i, c = 4 * (tid & 7);
-      float v[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+      float v[4] = {ra[bb][i].x, ra[bb][i].y, ra[bb][i].z, ra[bb][i].w};
+      if (!aok[i]) v[0] = v[1] = v[2] = v[3] = 0.f;
       // exact residuals in float32: v - hi and (v - hi) - mid have at most 16
       // and 8 significant bits beyond the parts already taken
       us4 part[NA];
@@ -270,7 +288,8 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
     for (int i = 0; i < 2; ++i) {
       int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a][off(r, c >> 3)]) = rb[a][i];
+      for (int a = 0; a < NA; ++a)
+        *reinterpret_cast<uint4*>(&Bs[a][off(r, c >> 3)]) = bok[i] ? rb[a][i] : uint4{0, 0, 0, 0};
     }
   };
 
@@ -279,40 +298,48 @@ __global__ __launch_bounds__(NT) void k_gemm_bf16(const float* __restrict__ A,
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (k0 + BK < K) gload(k0 + BK);
-    bf8 a[NA][4], b[NA][4];
+  auto compute = [&]() {
+    // B fragments held for the tile, A fragments one row block at a time
+    bf8 b[NA][4];
 #pragma unroll
-    for (int x = 0; x < NA; ++x) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        a[x][i] = *reinterpret_cast<const bf8*>(&As[x][off(wm0 + 16 * i + lr, lk)]);
+    for (int x = 0; x < NA; ++x)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x][off(wn0 + 16 * j + lr, lk)]);
-    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      bf8 a[NA];
+#pragma unroll
+      for (int x = 0; x < NA; ++x) a[x] = *reinterpret_cast<const bf8*>(&As[x][off(wm0 + 16 * i + lr, lk)]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         // terms of size 2^-16 and above (relative): a_x b_y with x + y < NA,
         // the smallest first
         if constexpr (NA == 3) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j], acc[i][j], 0, 0, 0);
         }
         if constexpr (NA >= 2) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], acc[i][j], 0, 0, 0);
         }
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc[i][j], 0, 0, 0);
       }
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  aload(I0{}, 0);
+  bload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sstore(I0{});
+    __syncthreads();
+    if (k0 + BK < K) {
+      aload(I0{}, k0 + BK);
+      bload(k0 + BK);
+    }
+    compute();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)

@@ -1089,35 +1089,48 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
   const int64_t ld = 2 * (int64_t)sx;          // row length of the buffer and of B^T
   const int64_t part = ld * ld;                // elements per bf16 part of B^T
 
-  // two k chunks in flight in registers (the W rows come from HBM once per
-  // tile, so one chunk of prefetch leaves most of the latency exposed)
+  // the W rows come from HBM once per tile: two k chunks of them in flight,
+  // the B^T chunk (shared by every tile, from L2) one.  Rows beyond the
+  // buffer load a valid row and are zeroed afterwards, so the loads carry no
+  // branches and the waits can count them.
   float4 ra[2][4];
-  uint4 rb[2][NA][2];
+  uint4 rb[NA][2];
+  int64_t arow[4];
+  bool aok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gm = m0 + (tid >> 3) + 32 * i;
+    aok[i] = gm < rows;
+    arow[i] = (aok[i] ? gm : rows - 1) * ld + 4 * (tid & 7);
+  }
+  int64_t brow[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int nl = (tid >> 2) + 64 * i;      // local column: real parts of the window, then imaginary
+    const int np = nl < FAR_NW ? klo + nl : sx + klo + (nl - FAR_NW);
+    brow[i] = (int64_t)np * ld + 8 * (tid & 3);
+  }
   auto gk = [&](int kk) { return kk < L ? khi + kk : sx + khi + (kk - L); };
-  auto gload = [&](auto bufc, int kk) {
+  auto aload = [&](auto bufc, int kk) {
     constexpr int bb = decltype(bufc)::value;
     const int k = gk(kk);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t gm = m0 + (tid >> 3) + 32 * i;
-      ra[bb][i] = (gm < rows) ? *reinterpret_cast<const float4*>(spec + gm * ld + k + 4 * (tid & 7))
-                              : float4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int i = 0; i < 4; ++i) ra[bb][i] = *reinterpret_cast<const float4*>(spec + arow[i] + k);
+  };
+  auto bload = [&](int kk) {
+    const int k = gk(kk);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int nl = (tid >> 2) + 64 * i;      // local column: real parts of the window, then imaginary
-      const int np = nl < FAR_NW ? klo + nl : sx + klo + (nl - FAR_NW);
-      const int64_t o = (int64_t)np * ld + k + 8 * (tid & 3);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int a = 0; a < NA; ++a) rb[bb][a][i] = *reinterpret_cast<const uint4*>(Bt + a * part + o);
-    }
+      for (int a = 0; a < NA; ++a) rb[a][i] = *reinterpret_cast<const uint4*>(Bt + a * part + brow[i] + k);
   };
   auto sstore = [&](auto bufc) {
     constexpr int bb = decltype(bufc)::value;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 3) + 32 * i, c = 4 * (tid & 7);
-      const float v[4] = {ra[bb][i].x, ra[bb][i].y, ra[bb][i].z, ra[bb][i].w};
+      float v[4] = {ra[bb][i].x, ra[bb][i].y, ra[bb][i].z, ra[bb][i].w};
+      if (!aok[i]) v[0] = v[1] = v[2] = v[3] = 0.f;
       us4 prt[NA];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1135,7 +1148,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
     for (int i = 0; i < 2; ++i) {
       const int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a * BN * BK + off(r, c >> 3)]) = rb[bb][a][i];
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a * BN * BK + off(r, c >> 3)]) = rb[a][i];
     }
   };
 
@@ -1145,41 +1158,46 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   auto compute = [&]() {
-    bf8 a[NA][4], b[NA][4];
+    // B fragments held for the tile, A fragments one row block at a time
+    bf8 b[NA][4];
 #pragma unroll
-    for (int x = 0; x < NA; ++x) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[x][i] = *reinterpret_cast<const bf8*>(&As[x * BM * BK + off(wm0 + 16 * i + lr, lk)]);
+    for (int x = 0; x < NA; ++x)
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[x][j] = *reinterpret_cast<const bf8*>(&Bs[x * BN * BK + off(wn0 + 16 * j + lr, lk)]);
-    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      bf8 a[NA];
+#pragma unroll
+      for (int x = 0; x < NA; ++x) a[x] = *reinterpret_cast<const bf8*>(&As[x * BM * BK + off(wm0 + 16 * i + lr, lk)]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc[i][j], 0, 0, 0);
       }
+    }
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
-  gload(I0{}, 0);
-  if (BK < K2) gload(I1{}, BK);
+  aload(I0{}, 0);
+  bload(0);
+  if (BK < K2) aload(I1{}, BK);
   for (int kk = 0; kk < K2; kk += 2 * BK) {
     __syncthreads();
     sstore(I0{});
     __syncthreads();
-    if (kk + 2 * BK < K2) gload(I0{}, kk + 2 * BK);
+    if (kk + 2 * BK < K2) aload(I0{}, kk + 2 * BK);
+    if (kk + BK < K2) bload(kk + BK);
     compute();
     if (kk + BK >= K2) break;
     __syncthreads();
     sstore(I1{});
     __syncthreads();
-    if (kk + 3 * BK < K2) gload(I1{}, kk + 3 * BK);
+    if (kk + 3 * BK < K2) aload(I1{}, kk + 3 * BK);
+    if (kk + 2 * BK < K2) bload(kk + 2 * BK);
     compute();
   }
   // the accumulators through LDS (reusing the staging buffers), 64 rows at a
