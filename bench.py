@@ -357,7 +357,7 @@ def timed_leg(pd, call, args, torch):
 
 
 # kernels behind a stage where it differs from the ParaDiag-II default
-LEG_KERNEL = {"hyb": {"fft_fwd": "k_time_gemm (V^-1)", "fft_inv": "k_time_gemm (V)"},
+LEG_KERNEL = {"hyb": {"fft_fwd": "k_time_gemm (V^-1)", "fft_inv": "k_time_gemm (V)", "line_solve": "k_line_solve"},
               "oc": {"fft_fwd": "k_time_gemm (DFT) + k_oc_mix", "fft_inv": "k_oc_unmix + k_time_gemm (inverse DFT)",
                      "line_solve": "k_line_solve"},
               "par": {"fine": "k_parareal_fine", "line_solve": "k_line_solve"},
@@ -372,13 +372,18 @@ def leg_roofline(leg, dominant, timed):
     tms, cnt, by, fl = timed
     cnt = max(cnt, 1)
     avg_s = tms / 1e3 / cnt
-    if (dominant in ("fft_fwd", "fft_inv") and leg in ("hyb", "oc")) or dominant in ("xform_fwd", "xform_inv"):
+    # an x-transform of a sine basis with nx + 1 a power of two is a DST by FFT
+    # (a few flops per byte): HBM-bound; otherwise a dense product on MFMA
+    dense_xform = dominant in ("xform_fwd", "xform_inv") and fl >= 16.0 * by
+    if (dominant in ("fft_fwd", "fft_inv") and leg in ("hyb", "oc")) or dense_xform:
         bound, achieved, peak, unit = "mfma", fl / cnt / avg_s / 1e12, PEAK["mfma_TFs"]["fp64"], "TFLOP/s"
     elif dominant == "fine":
         bound, achieved, peak, unit = "alu", fl / cnt / avg_s / 1e12, PEAK["vector_TFs"]["fp64"], "TFLOP/s"
     else:
         bound, achieved, peak, unit = "hbm", by / cnt / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
     kernel = LEG_KERNEL.get(leg, {}).get(dominant, STAGE_KERNEL.get(dominant, dominant))
+    if dominant in ("xform_fwd", "xform_inv") and not dense_xform:
+        kernel = "k_dst"
     return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "kernel": kernel, "stage": dominant, "launches": cnt,
             "avg_launch_ms": round(tms / cnt, 5), "algorithmic_flops_per_launch": fl / cnt,

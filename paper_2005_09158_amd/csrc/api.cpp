@@ -261,6 +261,8 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out, double
       if (!complex_schur(n, H, Q)) { set_error("Schur iteration did not converge"); return PD_ERR_BREAKDOWN; }
       T = H;
     }
+    // DST-I by FFT: lengths 2 (nx + 1) = 8 .. 4096, a power of two
+    pl->dst = !pl->schur && n >= 3 && ((n + 1) & n) == 0 && 2 * (n + 1) <= 4096;
     pl->op[0].Q = Q;
     pl->op[0].Tm = T;
     // K_x^T = conj(Q) T^T Q^T = (conj(Q) J)(J T^T J)(J Q^T): Schur form of the transpose
@@ -289,6 +291,7 @@ size_t tables_bytes(const Plan& pl) {
   b += align_up(sizeof(double2) * g.nt);              // twiddles f64
   b += align_up(sizeof(float2) * g.nt);               // twiddles f32
   b += align_up(sizeof(double2) * 2 * g.F);           // lam
+  if (pl.dst) b += align_up(spec_elem_bytes(pl.prec) * 2 * (g.nx + 1));   // DST twiddles
   if (pl.hybrid) {
     b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt, g.nt));   // V^{-1}, V (fragment order)
     b += 2 * align_up(sizeof(double) * 5 * g.nt);                         // banded rows of B, B^T
@@ -416,6 +419,10 @@ static double time_flops(const Plan& pl) {
 static double xform_flops(const Plan& pl) {
   const Geom& g = pl.g;
   double rows = (double)g.B * g.F * g.sy;
+  if (pl.dst) {   // one complex FFT of length 2 (nx + 1) per row (both halves)
+    const double n2 = 2.0 * (g.sx + 1);
+    return rows * 5.0 * n2 * std::log2(n2);
+  }
   return pl.schur ? 2.0 * rows * (2.0 * g.sx) * (2.0 * g.sx) : 2.0 * (2.0 * rows) * g.sx * g.sx;
 }
 static double sweep_flops(const Plan& pl) {
@@ -1084,6 +1091,7 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
   pl->d_tw64 = (double2*)take(sizeof(double2) * g.nt);
   pl->d_tw32 = (float2*)take(sizeof(float2) * g.nt);
   pl->d_lam = (double2*)take(sizeof(double2) * 2 * g.F);
+  if (pl->dst) pl->d_dtw = take(spec_elem_bytes(pl->prec) * 2 * (g.nx + 1));
   up(pl->d_gam, pl->gam.data(), sizeof(double) * g.nt);
   up(pl->d_invgam, pl->invgam.data(), sizeof(double) * g.nt);
   {
@@ -1097,6 +1105,18 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
     }
     up(pl->d_tw64, t64.data(), sizeof(double2) * g.nt);
     up(pl->d_tw32, t32.data(), sizeof(float2) * g.nt);
+    if (pl->dst) {   // first half of the length-2(nx+1) table, in the compute precision
+      const int h = g.nx + 1;
+      std::vector<double2> d64(h);
+      std::vector<float2> d32(h);
+      for (int k = 0; k < h; ++k) {
+        const double a = -PI * k / h;
+        d64[k] = double2{std::cos(a), std::sin(a)};
+        d32[k] = float2{(float)std::cos(a), (float)std::sin(a)};
+      }
+      if (pl->prec == Prec::F64) up(pl->d_dtw, d64.data(), sizeof(double2) * h);
+      else up(pl->d_dtw, d32.data(), sizeof(float2) * h);
+    }
     std::vector<double2> lam(2 * g.F);
     for (int n = 0; n < g.F; ++n) {
       lam[n] = double2{pl->lam1[n].real(), pl->lam1[n].imag()};

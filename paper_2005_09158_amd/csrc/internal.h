@@ -128,6 +128,10 @@ struct Plan {
   Geom g;
   Prec prec;
   bool schur = false;     // non-normal x factor: Schur back-sweep in Step-(b)
+  // sine basis with nx + 1 a power of two: the x-transform is a DST-I computed
+  // by an FFT of length 2 (nx + 1) instead of the dense product
+  bool dst = false;
+  void* d_dtw = nullptr;  // exp(-2 pi i k / (2 (nx + 1))), k < nx + 1, compute precision
   int L = 2;              // bands of the time stencil
   double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
   double theta = 1.0;
@@ -215,6 +219,8 @@ void time_gemm(const Plan& pl, bool forward, const double* table, const void* in
 std::vector<double> time_gemm_fragments(const std::vector<double>& W, int m, int k);
 size_t time_gemm_fragment_elems(int m, int k);
 // Step-(b) pieces
+// the x-transform of a sine-basis plan with pl.dst set (forward = inverse)
+void dst_transform(const Plan& pl, const void* in, void* out, hipStream_t s);
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
            hipStream_t s);
 void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);

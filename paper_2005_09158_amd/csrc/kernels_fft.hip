@@ -736,6 +736,71 @@ void launch_inv(const Plan& pl, const T* spec, Tout* z, int accumulate, int reve
 #undef PD_INV
 }
 
+// Step-(b) x-transform of a sine basis by FFT (nx + 1 a power of two).  For
+// a real row x_1 .. x_n, the DST-I S_k = sum_j x_j sin(pi j k / (n+1)),
+// k = 1..n, is -Im(Z_k) / 2 for the FFT Z of the odd extension
+// z = (0, x_1 .. x_n, 0, -x_n .. -x_1) of length N2 = 2 (n+1).  The real and
+// imaginary halves of a spectral row go in as the real and imaginary parts
+// of one z: both extensions are odd, so each transform is purely imaginary and
+// Z_k = -2i S_k(x_re) + 2 S_k(x_im) keeps them apart.  The basis is
+// sqrt(2/(n+1)) sin(pi j k/(n+1)) (orthonormal and symmetric), so the
+// forward and the inverse x-transform are this same map.  ncol rows per
+// workgroup, ncol N2 <= EPT NT / 2 (four workgroups per CU), columns in LDS
+// with an odd stride.
+template <typename T>
+__global__ __launch_bounds__(NT, 2) void k_dst(const T* __restrict__ in, T* __restrict__ out, int64_t rows, int n,
+                                               int logN2, int ncol, T scale,
+                                               const typename V2<T>::t* __restrict__ tw) {
+  using C = typename V2<T>::t;
+  constexpr int EPT = FftTraits<T>::EPT;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
+  const int N2 = 1 << logN2, ld = N2 + 1;
+  C* smtw = sm + ncol * ld;
+  stage_twiddles(smtw, tw, N2);
+  const int64_t r0 = (int64_t)blockIdx.x * ncol;
+  const int64_t rs = 2 * (int64_t)n;   // row length of the buffer: n real, then n imaginary parts
+  // the odd extensions: each input value read once, stored at j and N2 - j.
+  // All of a thread's loads (at most EPT / 2 pairs, since ncol N2 <= EPT NT)
+  // are issued before the first store; out-of-range ones read a valid
+  // address and are dropped, so they carry no branches.
+  constexpr int MAXE = EPT / 2;
+  const int tot = ncol * n;
+  C v[MAXE];
+#pragma unroll
+  for (int u = 0; u < MAXE; ++u) {
+    const int e = min((int)threadIdx.x + u * NT, tot - 1);
+    const int c = e / n, i = e - c * n;
+    const int64_t r = min(r0 + c, rows - 1);
+    const T* row = in + r * rs;
+    v[u] = C{row[i], row[n + i]};
+  }
+#pragma unroll
+  for (int u = 0; u < MAXE; ++u) {
+    const int e = (int)threadIdx.x + u * NT;
+    if (e < tot) {
+      const int c = e / n, i = e - c * n;
+      const C w = (r0 + c < rows) ? v[u] : C{0, 0};
+      sm[c * ld + i + 1] = w;
+      sm[c * ld + N2 - 1 - i] = C{-w.x, -w.y};
+    }
+  }
+  for (int c = threadIdx.x; c < ncol; c += NT) {
+    sm[c * ld] = C{0, 0};
+    sm[c * ld + n + 1] = C{0, 0};
+  }
+  __syncthreads();
+  fft_columns<T, EPT>(sm, ncol, ColUniform{ld}, N2, logN2, smtw);
+  for (int e = threadIdx.x; e < ncol * 2 * n; e += NT) {
+    const int c = e / (2 * n), q = e - c * 2 * n;
+    const int64_t r = r0 + c;
+    if (r >= rows) continue;
+    const bool imag = q >= n;
+    const C z = sm[c * ld + (imag ? q - n : q) + 1];
+    out[r * rs + q] = imag ? scale * z.x : -scale * z.y;
+  }
+}
+
 }  // namespace
 
 void fft_time_forward(const Plan& pl, const double* x, const double* bscale, int bstride, void* spec,
@@ -758,6 +823,28 @@ void fft_time_inverse(const Plan& pl, const void* spec, void* z, bool z_is_f32, 
       launch_inv<float, float>(pl, (const float*)spec, (float*)z, accumulate, reverse, s, pl.d_tw32);
     else
       launch_inv<float, double>(pl, (const float*)spec, (double*)z, accumulate, reverse, s, pl.d_tw32);
+  }
+}
+
+void dst_transform(const Plan& pl, const void* in, void* out, hipStream_t s) {
+  const Geom& g = pl.g;
+  const int n = g.sx, N2 = 2 * (n + 1);
+  int logN2 = 0;
+  while ((1 << logN2) < N2) ++logN2;
+  const int64_t rows = (int64_t)g.B * g.F * g.sy;
+  const double scale = 0.5 * std::sqrt(2.0 / (n + 1));
+  if (pl.prec == Prec::F64) {
+    const int ncol = std::max(1, FftTraits<double>::EPT * NT / (2 * N2));   // half the pass capacity: four workgroups per CU
+    const size_t lds = sizeof(double2) * ((size_t)ncol * (N2 + 1) + N2 / 2);
+    lds_limit((const void*)k_dst<double>, lds);
+    k_dst<double><<<(unsigned)((rows + ncol - 1) / ncol), NT, lds, s>>>(
+        (const double*)in, (double*)out, rows, n, logN2, ncol, scale, (const double2*)pl.d_dtw);
+  } else {
+    const int ncol = std::max(1, FftTraits<float>::EPT * NT / (2 * N2));   // half the pass capacity: four workgroups per CU
+    const size_t lds = sizeof(float2) * ((size_t)ncol * (N2 + 1) + N2 / 2);
+    lds_limit((const void*)k_dst<float>, lds);
+    k_dst<float><<<(unsigned)((rows + ncol - 1) / ncol), NT, lds, s>>>(
+        (const float*)in, (float*)out, rows, n, logN2, ncol, (float)scale, (const float2*)pl.d_dtw);
   }
 }
 

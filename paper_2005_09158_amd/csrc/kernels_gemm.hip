@@ -365,6 +365,10 @@ void launch_gemm_bf16(const float* A, const unsigned short* Bt, float* C, int64_
 
 void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void* out,
            hipStream_t s) {
+  if (pl.dst) {   // sine basis, nx + 1 a power of two: DST-I by FFT
+    dst_transform(pl, in, out, s);
+    return;
+  }
   const Geom& g = pl.g;
   const void* Bt = forward ? op.g_fwd : op.g_inv;
   int64_t rows = (int64_t)g.B * g.F * g.sy;   // complex rows of length sx

@@ -120,6 +120,28 @@ def test_windowed_sweep_shapes(nx, ny):
     assert errs["fp32_bf16gemm"] <= 4 * errs["fp32"] + 1e-6
 
 
+# Sine-basis x-transform by FFT (nx + 1 a power of two: a DST-I as one complex
+# FFT of length 2 (nx + 1) per spectral row, both halves at once): FFT lengths
+# 16 .. 1024, odd and even row counts, every precision.  Same tolerances as
+# the dense product it replaces.
+DST_SHAPES = [(7, 9), (15, 40), (63, 17), (255, 12), (511, 9)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_bf16gemm"])
+@pytest.mark.parametrize("nx,ny", DST_SHAPES)
+def test_dst_xform_shapes(nx, ny, prec):
+    announce(f"DST x-transform {nx}x{ny} {prec}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nt=8, scheme="tr", T=0.5, nu=0.05, ay=0.7, alpha=1e-2)
+    torch, pd, prob = make(cfg, prec)
+    r = np.random.default_rng(nx + ny).standard_normal((prob.nt, prob.nspace))
+    z_ref = o_prec.three_steps(prob, r)
+    z = pd.apply_precond(to_gpu(torch, r, pd.shape))
+    torch.cuda.synchronize()
+    err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
+    print(f"  rel err {err:.3e}")
+    assert err < PREC_TOL[prec]
+
+
 # Line-solver shapes (sine basis): lines of 256 .. 512 rows take 8 rows per
 # lane (32 or 64 lanes per line), 1024 and 2048 rows take 16 and 32 rows per
 # lane (tiles of 4 modes; 135 KiB of LDS at 2048 rows in float64), a ragged
