@@ -160,7 +160,13 @@ __global__ __launch_bounds__(NT) void k_time_gemm(const double* __restrict__ Wf,
 
 }  // namespace
 
-int time_gemm_rows(int m) { return m >= 256 ? 256 : 64; }
+// Row tile of the time product: 256 rows (each data tile feeds four times the
+// MFMA work) unless padding m to a multiple of 256 wastes more than a tenth
+// beyond what 64-row tiles pad (m = 258: 512 against 320 rows)
+int time_gemm_rows(int m) {
+  const int p256 = 256 * ((m + 255) / 256), p64 = 64 * ((m + 63) / 64);
+  return (m >= 256 && 10 * p256 <= 11 * p64) ? 256 : 64;
+}
 
 // W (m x k, row-major) in MFMA fragment order for workgroups of
 // time_gemm_rows(m) rows: frag[(rb * (Kpad/4) + ks) * 64 + lane] =
