@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(NT) void k_line_lu(T* __restrict__ lu, const double
 // through LDS so that each thread can combine a mode's real and imaginary
 // parts and apply the complex lambda2 of its row's frequency.  Needs
 // nx % 32 == 0 (k chunks do not straddle the two halves; 16-byte loads).
-constexpr int FAR_NW = SWEEP_WINDOW;
+constexpr int FAR_NW = 64;   // modes per column tile; a window takes SWEEP_WINDOW / 64 of them
 
 __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, const unsigned short* __restrict__ Bt,
                                                   const double2* __restrict__ lam, int64_t rows, int F, int sx,
@@ -1084,6 +1084,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
+  klo += FAR_NW * (int)blockIdx.y;             // this tile's 64 modes of the window
   const int L = sx - khi;                      // solved modes beyond the window
   const int K2 = 2 * L;
   const int64_t ld = 2 * (int64_t)sx;          // row length of the buffer and of B^T
@@ -1406,8 +1407,8 @@ void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
   for (int khi = g.sx; khi > 0; khi -= SWEEP_WINDOW) {
     const int klo = khi - SWEEP_WINDOW;
     if (khi < g.sx)
-      k_sweep_far<<<tiles, NT, 0, s>>>((float*)spec, (const unsigned short*)op.tfar, pl.d_lam, rows, g.F,
-                                       g.sx, g.sy, klo, khi);
+      k_sweep_far<<<dim3(tiles, SWEEP_WINDOW / FAR_NW), NT, 0, s>>>((float*)spec, (const unsigned short*)op.tfar,
+                                                                   pl.d_lam, rows, g.F, g.sx, g.sy, klo, khi);
     launch<float>(pl, op, (float*)spec, s, klo, khi);
   }
 }
