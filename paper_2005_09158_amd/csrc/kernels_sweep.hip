@@ -544,9 +544,11 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
     __syncthreads();   // block kb+1 in global memory; its LDS buffer is free; block kb's pivots staged
     // wave 0: block kb (carrying its coupling to every mode beyond block kb+1)
-    // into registers
+    // into registers; in a window before the coupling waves overwrite the one
+    // tile buffer, else inside wave 0's branch (loaded here, the lines would
+    // stay live across the coupling waves' code and spill it)
     Cx<T> d[NB][R];
-    if (wave == 0) {
+    auto load_block = [&]() {
       const int p = lane % P;
 #pragma unroll
       for (int q = 0; q < NB; ++q)
@@ -555,8 +557,11 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
           const int idx = q * ldy + p * (R + 1) + i;
           d[q][i] = (lane < P && q < nk) ? Cx<T>{cre[idx], cim[idx]} : cz<T>();
         }
+    };
+    if constexpr (WIN) {
+      if (wave == 0) load_block();
+      __syncthreads();   // the single tile buffer is free for block kb-1
     }
-    if constexpr (WIN) __syncthreads();   // the single tile buffer is free for block kb-1
     const int k0n = k0 - NB;   // next block (always full) when kb > blo
     // windowed: no pairing, every step couples block kb-1 to the rest of the window
     const bool far = WIN || ((st + phase) & 1) == 0;
@@ -690,24 +695,33 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
             iv[i] = (active && p * R + i < sy) ? Cx<T>{src[2 * i], src[2 * i + 1]} : c1<T>();
         }
       };
+      if constexpr (!WIN) load_block();
       Cx<T> ivn[R];
       load_inv(nk - 1, ivn);
+      // coupling of the whole block to block kb+1 (solved in the previous
+      // step; nothing in the first): it does not depend on this block's own
+      // lines, so it runs as one batch before them, one solved line of block
+      // kb+1 at a time, instead of on the chain of solves
+      if (st > 0) {
+#pragma unroll
+        for (int jq = 0; jq < NB; ++jq) {
+          Cx<T> x[R];
+#pragma unroll
+          for (int i = 0; i < R; ++i) x[i] = wsol[(jq * R + i) * 64 + lane];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const Cx<T> t = tnc[q * NB + jq];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              d[q][i].x = fma(-t.x, x[i].x, fma(t.y, x[i].y, d[q][i].x));
+              d[q][i].y = fma(-t.x, x[i].y, fma(-t.y, x[i].x, d[q][i].y));
+            }
+          }
+        }
+      }
 #pragma unroll
       for (int q = NB - 1; q >= 0; --q) {
         if (q < nk) {
-          // coupling to block kb+1 (zero coefficients in the first step)
-          if (st > 0) {
-#pragma unroll
-            for (int jq = 0; jq < NB; ++jq) {
-              const Cx<T> t = tnc[q * NB + jq];
-#pragma unroll
-              for (int i = 0; i < R; ++i) {
-                const Cx<T> x = wsol[(jq * R + i) * 64 + lane];
-                d[q][i].x = fma(-t.x, x.x, fma(t.y, x.y, d[q][i].x));
-                d[q][i].y = fma(-t.x, x.y, fma(-t.y, x.x, d[q][i].y));
-              }
-            }
-          }
           Cx<T> iv[R];
 #pragma unroll
           for (int i = 0; i < R; ++i) iv[i] = ivn[i];
