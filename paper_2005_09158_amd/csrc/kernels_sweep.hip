@@ -815,7 +815,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
 }
 
 template <typename T, int R, int P, int NB, int BK, int RB, bool VEC>
-__global__ __launch_bounds__(NT, 2) void k_schur_sweep_wide(T* __restrict__ spec, const double2* __restrict__ lam,
+__global__ __launch_bounds__(NT, (sizeof(T) == 8 && R >= 8) ? 1 : 2) void k_schur_sweep_wide(T* __restrict__ spec, const double2* __restrict__ lam,
                                                     const double2* __restrict__ tk,
                                                     const T* __restrict__ tup,
                                                     const T* __restrict__ lu, double lo, double di,
