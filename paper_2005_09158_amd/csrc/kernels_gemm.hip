@@ -170,8 +170,107 @@ __global__ __launch_bounds__(NT) void k_gemm(const Ts* __restrict__ A, const Tc*
       }
 }
 
+// The float64 / float32 product for aligned shapes (K a multiple of 32, N of
+// 64): 64 x 64 x 32 tiles, 16-byte operand loads without branches (rows past
+// M load row M-1 and are zeroed), the next k tile loaded into registers while
+// the current one is multiplied, LDS rows padded by one 16-byte unit.  Twice
+// the k depth of k_gemm per barrier pair: 32 float64 MFMAs per wave and tile.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gemm_pf(const T* __restrict__ A, const T* __restrict__ Bt,
+                                                T* __restrict__ C, int64_t M, int N, int K, int ntn) {
+  using MF = Mfma<T>;
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int VW = 16 / sizeof(T);                 // values per 16-byte load
+  constexpr int LDK = BK + VW;                       // padded row
+  constexpr int PER = BM * BK / (NT * VW);           // 16-byte loads per thread and operand
+  typedef T V __attribute__((ext_vector_type(VW)));
+  __shared__ __align__(16) T As[BM * LDK];
+  __shared__ __align__(16) T Bs[BN * LDK];
+  const int bid = blockIdx.x;
+  const int tn = bid % ntn;
+  const int64_t m0 = (int64_t)(bid / ntn) * BM;
+  const int n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int UPR = BK / VW;                       // 16-byte units per row
+  int64_t aoff[PER];
+  bool aok[PER];
+  int boff[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT, r = e / UPR, c = (e % UPR) * VW;
+    const int64_t gm = m0 + r;
+    aok[u] = gm < M;
+    aoff[u] = (aok[u] ? gm : M - 1) * K + c;
+    boff[u] = (n0 + r) * K + c;
+  }
+  V ra[PER], rb[PER];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      ra[u] = *reinterpret_cast<const V*>(A + aoff[u] + k0);
+      rb[u] = *reinterpret_cast<const V*>(Bt + boff[u] + k0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT, r = e / UPR, c = (e % UPR) * VW;
+      V a = ra[u];
+      if (!aok[u]) a = V{};
+      *reinterpret_cast<V*>(&As[r * LDK + c]) = a;
+      *reinterpret_cast<V*>(&Bs[r * LDK + c]) = rb[u];
+    }
+  };
+  typename MF::acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += MF::KI) {
+      T af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[(wm0 + 16 * i + lr) * LDK + ks + lk];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[(wn0 + 16 * j + lr) * LDK + ks + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = MF::run(af[i], bf[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm0 + 16 * i + MF::row(lk, v);
+        const int gn = n0 + wn0 + 16 * j + lr;
+        if (gm < M) C[gm * N + gn] = acc[i][j][v];
+      }
+}
+
 template <typename Ts, typename Tc, int BM, int BN, int BK>
 void launch_gemm(const Ts* A, const Tc* Bt, Ts* C, int64_t M, int N, int K, hipStream_t s) {
+  if constexpr (std::is_same<Ts, Tc>::value && (std::is_same<Ts, double>::value || std::is_same<Ts, float>::value)) {
+    if (K % 32 == 0 && N % 64 == 0) {
+      const int ntn = N / 64;
+      const int64_t blocks = ((M + 63) / 64) * ntn;
+      k_gemm_pf<Ts><<<dim3((unsigned)blocks), NT, 0, s>>>(A, Bt, C, M, N, K, ntn);
+      return;
+    }
+  }
   int ntn = (N + BN - 1) / BN;
   int64_t ntm = (M + BM - 1) / BM;
   int64_t blocks = ntm * ntn;
