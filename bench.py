@@ -51,8 +51,10 @@ sys.path.insert(0, ROOT)
 
 PEAK = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
-    "mfma_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 2500.0, "fp32_bf16x1": 2500.0},
-    "vector_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 157.3, "fp32_bf16x1": 157.3},
+    "mfma_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 2500.0, "fp32_bf16x1": 2500.0,
+                 "fp32_fp16gemm": 2500.0},
+    "vector_TFs": {"fp64": 78.6, "fp32": 157.3, "fp32_bf16gemm": 157.3, "fp32_bf16x1": 157.3,
+                   "fp32_fp16gemm": 157.3},
 }
 
 # bound of each stage of the library's accounting
@@ -71,11 +73,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--mixed", default=None, choices=["fp32", "fp32_bf16gemm", "fp32_bf16x1"],
+    ap.add_argument("--mixed", default=None, choices=["fp32", "fp32_bf16gemm", "fp32_bf16x1", "fp32_fp16gemm"],
                     help="reduced-precision preconditioner (default: the workload's own; float32 "
                          "for the wave equation, split-bf16 x-transform otherwise)")
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--no-fp16-alt", action="store_true",
+                    help="skip the row-scaled split-fp16 variant timed beside the split-bf16 mixed mode")
     ap.add_argument("--legs", default="paradiag_i,oc_wave,parareal,nonlinear",
                     help="comma-separated extra legs after the main one (paradiag_i, oc_wave, "
                          "parareal, nonlinear), or 'none'")
@@ -534,6 +538,7 @@ def workload_name(cfg):
 
 
 DTYPE = {"fp32_bf16gemm": "f64 krylov + f32 fft/line solves + split-bf16 mfma x-transform",
+         "fp32_fp16gemm": "f64 krylov + f32 fft/line solves + row-scaled split-fp16 mfma x-transform",
          "fp32_bf16x1": "f64 krylov + f32 fft/line solves + bf16 mfma x-transform",
          "fp32": "f64 krylov + f32 preconditioner"}
 
@@ -589,6 +594,13 @@ def main():
         fp64, u64 = run_precision(cfg, "fp64", args, torch)
         print(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/solve iters {fp64['iters']} "
               f"resid {fp64['rel_resid']:.2e}", file=sys.stderr, flush=True)
+    # the row-scaled split-fp16 x-transform beside the workload's own mixed mode
+    # (reported, not `value`: the workload names bf16 products)
+    alt, ualt = None, None
+    if not args.no_fp16_alt and mixed_prec == "fp32_bf16gemm":
+        alt, ualt = run_precision(cfg, "fp32_fp16gemm", args, torch)
+        print(f"[bench] fp32_fp16gemm: {alt['ms_per_step']:.3f} ms/solve iters {alt['iters']} "
+              f"resid {alt['rel_resid']:.2e}", file=sys.stderr, flush=True)
     U = cfg.unknowns
     value = U / (mixed["ms_per_step"] / 1e3)
     line = {
@@ -618,6 +630,10 @@ def main():
         {k: round(v[0], 4) for k, v in fp64["stages"].items()},
         "roofline": roofline(mixed, cfg, args.traffic),
         "stage_roofline": stage_rooflines(mixed),
+        "mixed_fp16gemm": None if alt is None else {
+            "value": U / (alt["ms_per_step"] / 1e3), "ms_per_step": alt["ms_per_step"], "iters": alt["iters"],
+            "rel_resid": alt["rel_resid"], "dtype": DTYPE["fp32_fp16gemm"],
+            "stage_ms_per_step": {k: round(v[0], 4) for k, v in alt["stages"].items() if v[1]}},
     }
     if not args.no_oracle:
         print("[bench] float64 oracle: sequential time stepping of right-hand side 0", file=sys.stderr,
@@ -626,7 +642,8 @@ def main():
         line["error_vs_oracle"] = {
             "rhs": 0, "oracle": "sequential float64 time stepping, whole horizon",
             "mixed": error_vs_oracle(um, ref),
-            "fp64": None if u64 is None else error_vs_oracle(u64, ref)}
+            "fp64": None if u64 is None else error_vs_oracle(u64, ref),
+            "mixed_fp16gemm": None if ualt is None else error_vs_oracle(ualt, ref)}
         iters64 = max(fp64["iters"]) if fp64 else max(mixed["iters"])
         base, para = cpu_baselines(cfg, ref_dt, sample, iters64)
         if not args.no_cpu_baseline:

@@ -96,7 +96,11 @@ typedef enum {
                                  accurate).  Symmetric K_x only (sine basis): with a
                                  non-normal K_x setup returns PD_ERR_UNSUPPORTED, since
                                  the back-substitution over the Schur factor carries the
-                                 bf16 rounding into an error of order one */
+                                 bf16 rounding into an error of order one */,
+  PD_PREC_FP32_FP16GEMM = 4   /* as FP32; x-transform on fp16 MFMA with fp32 accumulation:
+                                 each row scaled by a power of two (its largest entry
+                                 near 2^14), both operands split into two fp16 parts,
+                                 three products (about 22 significant bits) */
 } paradiag_prec;
 
 typedef enum {

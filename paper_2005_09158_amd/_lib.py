@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "PD_OK", 1: "PD_NOT_CONVERGED", -1: "PD_ERR_INVALID", -2: "PD
                 -6: "PD_ERR_BREAKDOWN"}
 
 SCHEMES = {"be": 0, "tr": 1, "lf": 2, "hyb": 3, "hyb2": 4}
-PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2, "fp32_bf16x1": 3}
+PRECS = {"fp64": 0, "fp32": 1, "fp32_bf16gemm": 2, "fp32_bf16x1": 3, "fp32_fp16gemm": 4}
 MODES = {"fgmres": 0, "stationary": 1, "direct": 2, "parareal": 3, "nonlinear": 4}
 STAGES = ["fft_fwd", "xform_fwd", "line_solve", "xform_inv", "fft_inv", "matvec", "dot", "update",
           "other", "fine", "reaction"]

@@ -34,7 +34,9 @@ size_t compute_elem_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 
 // bytes of one x-transform matrix of `elems` entries in the compute format
 // (split bf16 keeps hi, mid and lo parts plus a float32 copy for ragged sizes)
 size_t gemm_matrix_bytes(Prec p, size_t elems) {
-  return p == Prec::BF16 ? elems * (2 + 2 + 2 + 4) : elems * compute_elem_bytes(p);
+  if (p == Prec::BF16) return elems * (2 + 2 + 2 + 4);   // three bf16 parts and a float32 copy
+  if (p == Prec::F16) return elems * (2 + 2 + 4);        // two fp16 parts and a float32 copy
+  return elems * compute_elem_bytes(p);
 }
 }  // namespace
 
@@ -91,7 +93,7 @@ static paradiag_status build_plan(const paradiag_problem* pr, Plan*& out, double
   }
   if (p.scheme < 0 || p.scheme > 4) { set_error("unknown scheme"); return PD_ERR_INVALID; }
   const bool hybrid = p.scheme == PD_HYBRID || p.scheme == PD_HYBRID_WAVE;
-  if (p.prec < 0 || p.prec > 3) { set_error("unknown precision"); return PD_ERR_INVALID; }
+  if (p.prec < 0 || p.prec > 4) { set_error("unknown precision"); return PD_ERR_INVALID; }
   if (p.reserved != 0) { set_error("reserved must be 0"); return PD_ERR_INVALID; }
   const bool oc = oc_gamma > 0.0;
   if (oc) {
@@ -292,6 +294,8 @@ size_t tables_bytes(const Plan& pl) {
   b += align_up(sizeof(float2) * g.nt);               // twiddles f32
   b += align_up(sizeof(double2) * 2 * g.F);           // lam
   if (pl.dst) b += align_up(spec_elem_bytes(pl.prec) * 2 * (g.nx + 1));   // DST twiddles
+  if (pl.prec == Prec::F16 && pl.p.dim == 2)
+    b += align_up(sizeof(float) * 2 * (size_t)g.B * g.F * g.sy);   // x-transform row scales
   if (pl.hybrid) {
     b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt, g.nt));   // V^{-1}, V (fragment order)
     b += 2 * align_up(sizeof(double) * 5 * g.nt);                         // banded rows of B, B^T
@@ -1092,6 +1096,8 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
   pl->d_tw32 = (float2*)take(sizeof(float2) * g.nt);
   pl->d_lam = (double2*)take(sizeof(double2) * 2 * g.F);
   if (pl->dst) pl->d_dtw = take(spec_elem_bytes(pl->prec) * 2 * (g.nx + 1));
+  if (pl->prec == Prec::F16 && pl->p.dim == 2)
+    pl->d_rowscale = (float*)take(sizeof(float) * 2 * (size_t)g.B * g.F * g.sy);
   up(pl->d_gam, pl->gam.data(), sizeof(double) * g.nt);
   up(pl->d_invgam, pl->invgam.data(), sizeof(double) * g.nt);
   {
@@ -1190,7 +1196,25 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
         if (pl->prec == Prec::F64) store_compute<double>(dst, src, s, keep);
         else if (pl->prec == Prec::F32) store_compute<float>(dst, src, s, keep);
         else if (pl->prec == Prec::BF16X1) store_compute<Bf16Bits>(dst, src, s, keep);
-        else {
+        else if (pl->prec == Prec::F16) {
+          // two fp16 parts of the entry times F16_BSCALE (the residual after the
+          // first is exact in float32), then a float32 copy
+          std::vector<uint16_t> part[2];
+          for (auto& v : part) v.resize(src.size());
+          for (size_t i = 0; i < src.size(); ++i) {
+            const float x = (float)src[i] * F16_BSCALE;
+            const _Float16 h = (_Float16)x;
+            const _Float16 l = (_Float16)(x - (float)h);
+            std::memcpy(&part[0][i], &h, 2);
+            std::memcpy(&part[1][i], &l, 2);
+          }
+          for (int a = 0; a < 2; ++a) {
+            std::vector<char> buf((const char*)part[a].data(), (const char*)part[a].data() + 2 * src.size());
+            hipMemcpyAsync((char*)dst + 2 * a * src.size(), buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+            keep.push_back(std::move(buf));
+          }
+          store_compute<float>((char*)dst + 4 * src.size(), src, s, keep);
+        } else {
           // three bf16 parts of the float32 value (hi, then the rounded
           // residuals mid and lo; the float32 subtractions are exact), then
           // a float32 copy

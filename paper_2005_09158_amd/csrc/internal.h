@@ -72,7 +72,10 @@ __device__ __forceinline__ BlockPos xcd_block() {
 // Numeric formats of the preconditioner.
 // BF16: operands split into three bf16 parts (six bf16 MFMAs per product);
 // BF16X1: single bf16 product.
-enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X1 = 3 };
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X1 = 3, F16 = 4 };
+// PD_PREC_FP32_FP16GEMM: the x-transform matrices are stored times this power
+// of two (their entries are at most 1 in magnitude) before the fp16 split
+constexpr float F16_BSCALE = 16384.0f;
 
 // Geometry of the spectral buffer [batch][F][sy][2][sx]: F = nt/2 + 1
 // frequencies, each slice a sy x sx complex field stored row-planar (a row
@@ -132,6 +135,7 @@ struct Plan {
   // by an FFT of length 2 (nx + 1) instead of the dense product
   bool dst = false;
   void* d_dtw = nullptr;  // exp(-2 pi i k / (2 (nx + 1))), k < nx + 1, compute precision
+  float* d_rowscale = nullptr;  // PD_PREC_FP32_FP16GEMM: power-of-two scale of every x-transform row
   int L = 2;              // bands of the time stencil
   double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
   double theta = 1.0;

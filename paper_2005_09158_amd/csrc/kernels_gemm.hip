@@ -40,6 +40,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
 
@@ -304,15 +305,19 @@ template <int SPLIT>
 __global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A,
                                                   const unsigned short* __restrict__ Bt,
                                                   float* __restrict__ C, int64_t M, int N, int K,
-                                                  int ntn, int64_t nblocks) {
+                                                  int ntn, int64_t nblocks, const float* __restrict__ rscale,
+                                                  float binv) {
   constexpr int BM = 128, BN = 128, BK = 32;
   // LDS rows of BK bf16 (64 bytes, four 16-byte chunks); chunk c of row r is
   // stored at position c ^ ((r >> 1) & 3), so that the eight rows one
   // fragment read touches per LDS cycle (and the rows of a staging write)
   // fall on distinct banks
   auto off = [](int r, int ch) { return r * BK + 8 * (ch ^ ((r >> 1) & 3)); };
-  // operand terms: 1 (plain bf16), 2 (hi + lo), 3 (hi + mid + lo)
-  constexpr int NA = (SPLIT == 6) ? 3 : (SPLIT == 3) ? 2 : 1;
+  // operand terms: 1 (plain bf16), 2 (hi + lo), 3 (hi + mid + lo); SPLIT = 16:
+  // fp16 hi + lo of rows scaled by a power of two (rscale) and of B (scaled
+  // by 1 / binv), three products a_hi b_hi + a_hi b_lo + a_lo b_hi
+  constexpr bool F16 = SPLIT == 16;
+  constexpr int NA = (SPLIT == 6) ? 3 : (SPLIT == 3 || F16) ? 2 : 1;
   __shared__ __align__(16) unsigned short As[NA][BM * BK];
   __shared__ __align__(16) unsigned short Bs[NA][BN * BK];
 
@@ -341,6 +346,9 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A
     aok[i] = gm < M;
     arow[i] = (aok[i] ? gm : M - 1) * K + 4 * (tid & 7);
   }
+  float rsc[4];   // SPLIT = 16: scales of this thread's staged rows
+#pragma unroll
+  for (int i = 0; i < 4; ++i) rsc[i] = F16 ? rscale[arow[i] / K] : 1.f;
   int64_t brow[2];
   bool bok[2];
 #pragma unroll
@@ -373,11 +381,18 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A
       us4 part[NA];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        float rest = v[q];
+        if constexpr (F16) {   // power-of-two row scale (exact), then hi and the exact residual
+          const float x = v[q] * rsc[i];
+          const _Float16 h = (_Float16)x;
+          part[0][q] = __builtin_bit_cast(unsigned short, h);
+          part[1][q] = __builtin_bit_cast(unsigned short, (_Float16)(x - (float)h));
+        } else {
+          float rest = v[q];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          part[a][q] = bf16_bits(rest);
-          if (a + 1 < NA) rest -= bf16_val(part[a][q]);
+          for (int a = 0; a < NA; ++a) {
+            part[a][q] = bf16_bits(rest);
+            if (a + 1 < NA) rest -= bf16_val(part[a][q]);
+          }
         }
       }
 #pragma unroll
@@ -414,6 +429,15 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A
       for (int j = 0; j < 4; ++j) {
         // terms of size 2^-16 and above (relative): a_x b_y with x + y < NA,
         // the smallest first
+        if constexpr (F16) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[1]), __builtin_bit_cast(h8, b[0][j]),
+                                                             acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[0]), __builtin_bit_cast(h8, b[1][j]),
+                                                             acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[0]), __builtin_bit_cast(h8, b[0][j]),
+                                                             acc[i][j], 0, 0, 0);
+          continue;
+        }
         if constexpr (NA == 3) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], acc[i][j], 0, 0, 0);
@@ -448,16 +472,42 @@ __global__ __launch_bounds__(NT, 2) void k_gemm_bf16(const float* __restrict__ A
       for (int v = 0; v < 4; ++v) {
         int64_t gm = m0 + wm0 + 16 * i + 4 * lk + v;
         int gn = n0 + wn0 + 16 * j + lr;
-        if (gm < M && gn < N) C[gm * N + gn] = acc[i][j][v];
+        if (gm < M && gn < N) C[gm * N + gn] = F16 ? acc[i][j][v] * (binv / rscale[gm]) : acc[i][j][v];
       }
+}
+
+// Power-of-two scale of each row of A (M rows of K floats, K % 4 == 0) that
+// brings its largest magnitude into [2^13, 2^14): one wave per row.  Zero
+// rows get 1.
+__global__ __launch_bounds__(NT) void k_rowscale(const float* __restrict__ A, int64_t M, int K,
+                                                 float* __restrict__ rscale) {
+  const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (row >= M) return;   // whole waves
+  const int lane = threadIdx.x & 63;
+  const float* a = A + row * K;
+  float m = 0.f;
+  for (int k = 4 * lane; k < K; k += 256) {
+    const float4 v = *reinterpret_cast<const float4*>(a + k);
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane == 0) {
+    int e = 0;
+    (void)frexpf(m, &e);   // m = f 2^e, f in [0.5, 1)
+    rscale[row] = m > 0.f ? ldexpf(1.f, 14 - e) : 1.f;
+  }
 }
 
 template <int SPLIT>
 void launch_gemm_bf16(const float* A, const unsigned short* Bt, float* C, int64_t M, int N, int K,
-                      hipStream_t s) {
+                      hipStream_t s, float* rscale = nullptr) {
   int ntn = (N + 127) / 128;
   int64_t nblocks = ((M + 127) / 128) * ntn;
-  k_gemm_bf16<SPLIT><<<dim3((unsigned)nblocks), NT, 0, s>>>(A, Bt, C, M, N, K, ntn, nblocks);
+  if constexpr (SPLIT == 16)
+    k_rowscale<<<dim3((unsigned)((M + NT / 64 - 1) / (NT / 64))), NT, 0, s>>>(A, M, K, rscale);
+  k_gemm_bf16<SPLIT><<<dim3((unsigned)nblocks), NT, 0, s>>>(A, Bt, C, M, N, K, ntn, nblocks, rscale,
+                                                             1.0f / F16_BSCALE);
 }
 
 }  // namespace
@@ -486,6 +536,14 @@ void xform(const Plan& pl, const SpaceOp& op, bool forward, const void* in, void
       break;
     case Prec::F32:
       launch_gemm<float, float, 64, 64, 16>((const float*)in, (const float*)Bt, (float*)out, M, N, K, s);
+      break;
+    case Prec::F16:
+      if (K % 32 == 0) {
+        launch_gemm_bf16<16>((const float*)in, (const unsigned short*)Bt, (float*)out, M, N, K, s, pl.d_rowscale);
+      } else {   // ragged K: the float32 product on the float32 copy after the two fp16 parts
+        const float* B32 = (const float*)((const unsigned short*)Bt + (size_t)2 * N * K);
+        launch_gemm<float, float, 64, 64, 16>((const float*)in, B32, (float*)out, M, N, K, s);
+      }
       break;
     case Prec::BF16:
     case Prec::BF16X1: {

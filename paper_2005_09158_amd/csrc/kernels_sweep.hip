@@ -1399,7 +1399,7 @@ void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s) {
 
 bool sweep_windowed(const Plan& pl) {
   const Geom& g = pl.g;
-  return pl.schur && pl.p.dim == 2 && pl.prec == Prec::BF16 && g.sx % SWEEP_WINDOW == 0 &&
+  return pl.schur && pl.p.dim == 2 && (pl.prec == Prec::BF16 || pl.prec == Prec::F16) && g.sx % SWEEP_WINDOW == 0 &&
          g.sx >= 2 * SWEEP_WINDOW && g.sx % 32 == 0;
 }
 

@@ -61,7 +61,7 @@ def test_cfg1_full():
     assert rel_err(pd.build_rhs(U0).cpu().numpy().reshape(p.nt, -1), b) < 1e-13
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_bf16gemm", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bf16gemm", "fp32", "fp32_fp16gemm"])
 def test_cfg2_full(prec):
     announce(f"cfg2 full solve {prec}")
     torch = torch_gpu()

@@ -39,7 +39,7 @@ CASES = {
     "2d-tr-schur-tall": dict(dim=2, nx=40, ny=300, nt=8, scheme="tr", T=0.5, nu=2e-2, ax=1.0, ay=0.5, alpha=1e-2),
 }
 
-PREC_TOL = {"fp64": 1e-11, "fp32": 2e-3, "fp32_bf16gemm": 2e-3, "fp32_bf16x1": 5e-2}
+PREC_TOL = {"fp64": 1e-11, "fp32": 2e-3, "fp32_bf16gemm": 2e-3, "fp32_bf16x1": 5e-2, "fp32_fp16gemm": 2e-3}
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
 
 
@@ -52,7 +52,7 @@ def _shape(prob, batch=1):
     return (batch, prob.nt, prob.ny, prob.nx)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_bf16gemm", "fp32_bf16x1"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_bf16gemm", "fp32_bf16x1", "fp32_fp16gemm"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_precond_parity(case, prec):
     announce(f"precond {case} {prec}")
@@ -109,15 +109,17 @@ def test_windowed_sweep_shapes(nx, ny):
     cfg = dict(dim=2, nx=nx, ny=ny, nt=8, scheme="tr", T=0.5, nu=0.05, ax=1.0, ay=0.5, alpha=1e-2)
     r = np.random.default_rng(11).standard_normal((cfg["nt"], nx * ny))
     errs = {}
-    for prec in ("fp32", "fp32_bf16gemm"):
+    for prec in ("fp32", "fp32_bf16gemm", "fp32_fp16gemm"):
         torch, pd, prob = make(cfg, prec)
         z = pd.apply_precond(to_gpu(torch, r, pd.shape))
         torch.cuda.synchronize()
         if prec == "fp32":
             z_ref = o_prec.three_steps(prob, r)
         errs[prec] = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
-    print(f"  rel err fp32 {errs['fp32']:.3e}, windowed split bf16 {errs['fp32_bf16gemm']:.3e}")
+    print(f"  rel err fp32 {errs['fp32']:.3e}, windowed split bf16 {errs['fp32_bf16gemm']:.3e}, "
+          f"split fp16 x-transform {errs['fp32_fp16gemm']:.3e}")
     assert errs["fp32_bf16gemm"] <= 4 * errs["fp32"] + 1e-6
+    assert errs["fp32_fp16gemm"] <= 4 * errs["fp32"] + 1e-6
 
 
 # Sine-basis x-transform by FFT (nx + 1 a power of two: a DST-I as one complex
