@@ -18,10 +18,12 @@ Tolerances (relative, max-abs error over max-abs reference):
 * solves: 1e-10 against the sequential time stepper at rtol 1e-12.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
-from oracle import adjoint as o_adj, operators as ops, precond as o_prec, rhs as o_rhs, solve as o_solve
+from oracle import Problem, adjoint as o_adj, operators as ops, precond as o_prec, rhs as o_rhs, solve as o_solve
 from tests.gpu_util import announce, make, rel_err, to_gpu
 from tests.bounds import line_condition
 
@@ -191,6 +193,33 @@ def test_time_fft_shapes(prec, nt):
     err = rel_err(z.cpu().numpy().reshape(prob.nt, -1), z_ref)
     print(f"  rel err {err:.3e}")
     assert err < PREC_TOL[prec]
+
+
+# The time FFTs over many tiles: 66 x 61 points (4026 = 251 x 16 + 10: a
+# ragged last tile of the 16-column tiles) in a batch of 8 at Nt = 512, several
+# thousand workgroups.  Batch entry b is (b + 1) r, so its result must be
+# (b + 1) z: a tile read from or written to the wrong entry shows as a wrong
+# scale.
+_MANY_TILES = dict(dim=2, nx=66, ny=61, nt=512, scheme="tr", T=1.0, nu=0.05, ax=0.7, alpha=1e-2)
+
+
+@functools.lru_cache(maxsize=1)
+def _many_tiles_oracle():
+    prob = Problem.from_kwargs(**_MANY_TILES)
+    r = np.random.default_rng(21).standard_normal((prob.nt, prob.nspace))
+    return r, o_prec.three_steps(prob, r)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_time_fft_many_tiles_batch(prec):
+    announce(f"fft tiles 66x61 nt=512 batch 8 {prec}")
+    torch, pd, prob = make(_MANY_TILES, prec, batch=8)
+    r, z_ref = _many_tiles_oracle()
+    rb = np.stack([(b + 1) * r for b in range(8)])
+    z = pd.apply_precond(to_gpu(torch, rb, pd.shape)).cpu().numpy().reshape(8, prob.nt, -1)
+    errs = [rel_err(z[b] / (b + 1), z_ref) for b in range(8)]
+    print(f"  rel err max {max(errs):.3e}")
+    assert max(errs) < PREC_TOL[prec]
 
 
 def test_adjoint_solve_long_time():
