@@ -296,6 +296,7 @@ size_t tables_bytes(const Plan& pl) {
   if (pl.dst) b += align_up(spec_elem_bytes(pl.prec) * 2 * (g.nx + 1));   // DST twiddles
   if (pl.prec == Prec::F16 && pl.p.dim == 2)
     b += align_up(sizeof(float) * 2 * (size_t)g.B * g.F * g.sy);   // x-transform row scales
+  if (sweep_windowed(pl)) b += align_up(sizeof(float) * (size_t)g.B * g.F * g.sy);   // row maxima of the sweep
   if (pl.hybrid) {
     b += 2 * align_up(sizeof(double) * time_gemm_fragment_elems(g.nt, g.nt));   // V^{-1}, V (fragment order)
     b += 2 * align_up(sizeof(double) * 5 * g.nt);                         // banded rows of B, B^T
@@ -313,7 +314,7 @@ size_t tables_bytes(const Plan& pl) {
       b += 2 * align_up(gemm_matrix_bytes(pl.prec, gm));              // g_fwd, g_inv
       if (pl.schur) b += align_up(2 * n * n * spec_elem_bytes(pl.prec));  // T (line precision)
       if (pl.schur) b += align_up((size_t)2 * g.F * n * g.sy * spec_elem_bytes(pl.prec));  // line LU
-      if (sweep_windowed(pl)) b += align_up((size_t)3 * 4 * n * n * 2);   // far-coupling B^T, bf16 parts
+      if (sweep_windowed(pl)) b += align_up((size_t)2 * 4 * n * n * 2);   // far-coupling B^T, fp16 parts
     }
   }
   b += 2 * align_up((size_t)g.spec_elems * spec_elem_bytes(pl.prec));
@@ -1098,6 +1099,7 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
   if (pl->dst) pl->d_dtw = take(spec_elem_bytes(pl->prec) * 2 * (g.nx + 1));
   if (pl->prec == Prec::F16 && pl->p.dim == 2)
     pl->d_rowscale = (float*)take(sizeof(float) * 2 * (size_t)g.B * g.F * g.sy);
+  if (sweep_windowed(*pl)) pl->d_rmax = (float*)take(sizeof(float) * (size_t)g.B * g.F * g.sy);
   up(pl->d_gam, pl->gam.data(), sizeof(double) * g.nt);
   up(pl->d_invgam, pl->invgam.data(), sizeof(double) * g.nt);
   {
@@ -1246,28 +1248,35 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
           // the windowed sweep's far-coupling product: B^T[m][k] with m < n the
           // real and m >= n the imaginary part of mode q = m mod n, and k < n
           // the real, k >= n the imaginary part of the solved mode:
-          // [[Tr, -Ti], [Ti, Tr]] row-wise; three bf16 parts (hi, mid, lo)
+          // [[Tr, -Ti], [Ti, Tr]] row-wise, times the power of two that brings
+          // its largest entry into [2^13, 2^14), as two fp16 parts (hi, lo)
           const size_t n2 = 2 * (size_t)n;
-          std::vector<double> part[3];
-          for (auto& v : part) v.assign(n2 * n2, 0.0);
+          double tmax = 0.0;
+          for (const cd& t : op.Tm) tmax = std::max({tmax, std::fabs(t.real()), std::fabs(t.imag())});
+          int e2 = 0;
+          (void)std::frexp(tmax, &e2);
+          const float tsc = tmax > 0.0 ? std::ldexp(1.0f, 14 - e2) : 1.0f;
+          op.tfar_inv = 1.0f / tsc;
+          std::vector<_Float16> part[2];
+          for (auto& v : part) v.assign(n2 * n2, (_Float16)0.0f);
           for (int q = 0; q < n; ++q)
             for (int j = 0; j < n; ++j) {
               const cd t = op.Tm[(size_t)q * n + j];
               const double e[4] = {t.real(), -t.imag(), t.imag(), t.real()};
               const size_t at[4] = {q * n2 + j, q * n2 + n + j, (n + q) * n2 + j, (n + q) * n2 + n + j};
               for (int c = 0; c < 4; ++c) {
-                float rest = (float)e[c];
-                for (int a = 0; a < 3; ++a) {
-                  uint32_t u = (uint32_t)to_bf16_bits(rest) << 16;
-                  float h;
-                  std::memcpy(&h, &u, 4);
-                  part[a][at[c]] = h;
-                  rest -= h;
-                }
+                const float x = (float)e[c] * tsc;   // exact: a power of two
+                const _Float16 h = (_Float16)x;
+                part[0][at[c]] = h;
+                part[1][at[c]] = (_Float16)(x - (float)h);
               }
             }
-          op.tfar = take(3 * n2 * n2 * 2);
-          for (int a = 0; a < 3; ++a) store_compute<Bf16Bits>((char*)op.tfar + 2 * a * n2 * n2, part[a], s, keep);
+          op.tfar = take(2 * n2 * n2 * 2);
+          for (int a = 0; a < 2; ++a) {
+            std::vector<char> buf((const char*)part[a].data(), (const char*)part[a].data() + 2 * n2 * n2);
+            hipMemcpyAsync((char*)op.tfar + 2 * a * n2 * n2, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+            keep.push_back(std::move(buf));
+          }
         }
       } else {
         op.tfar = nullptr;

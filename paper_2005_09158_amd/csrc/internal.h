@@ -106,8 +106,10 @@ struct SpaceOp {
   const void* tup = nullptr;    // Schur T (planar re/im, [2][nx][nx], compute format); null if diagonal
   void* lu = nullptr;           // Schur path: inverse LU pivots of every line, [F][nx][ny] complex
   // windowed back-sweep: the real block form of T for the far-coupling product,
-  // as three bf16 parts (hi, mid, lo), [3][2 nx][2 nx] (see sweep_windowed)
+  // times the power of two tfar_scale, as two fp16 parts (hi, lo),
+  // [2][2 nx][2 nx] (see sweep_windowed); tfar_inv = 1 / tfar_scale
   const void* tfar = nullptr;
+  float tfar_inv = 1.f;
   // host copies
   std::vector<cd> Q, Tm;        // nx*nx complex (row-major): K_x = Q T Q^H
 };
@@ -136,6 +138,7 @@ struct Plan {
   bool dst = false;
   void* d_dtw = nullptr;  // exp(-2 pi i k / (2 (nx + 1))), k < nx + 1, compute precision
   float* d_rowscale = nullptr;  // PD_PREC_FP32_FP16GEMM: power-of-two scale of every x-transform row
+  float* d_rmax = nullptr;      // windowed back-sweep: running maximum of every spectral row's solved modes
   int L = 2;              // bands of the time stencil
   double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
   double theta = 1.0;
@@ -231,7 +234,7 @@ void line_solve(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s);
 size_t schur_sweep_lds(const Plan& pl);   // dynamic LDS bytes of the back-sweep
 // true where the back-sweep runs in windows of SWEEP_WINDOW modes, their
-// coupling to later windows as one split-bf16 MFMA product (op.tfar needed)
+// coupling to later windows as one split-fp16 MFMA product (op.tfar needed)
 constexpr int SWEEP_WINDOW = 64;
 bool sweep_windowed(const Plan& pl);
 void schur_line_lu(const Plan& pl, const SpaceOp& op, hipStream_t s);  // fills op.lu

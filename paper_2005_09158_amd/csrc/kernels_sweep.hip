@@ -36,6 +36,7 @@ using namespace tri;
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short bf16_bits(float v) {
@@ -364,7 +365,7 @@ __device__ __forceinline__ void tile_rows_load(const T* slice, T* sre, T* sim, i
 // parts), 16-byte vectors when VEC and the block is full.
 template <typename T, int NB, int R, bool VEC>
 __device__ __forceinline__ void wsol_store(T* slice, const Cx<T>* wsol, int k0, int nk, int sx, int sy, int P,
-                                           int tid, int nthr) {
+                                           int tid, int nthr, float* __restrict__ rm) {
   for (int e = tid; e < P * R; e += nthr) {
     const int p = e % P, i = e / P, y = p * R + i;
     if (y >= sy) continue;
@@ -374,6 +375,13 @@ __device__ __forceinline__ void wsol_store(T* slice, const Cx<T>* wsol, int k0, 
       const Cx<T> v = wsol[(q * R + i) * 64 + p];
       re[q] = v.x;
       im[q] = v.y;
+    }
+    if (rm) {   // running maximum of the row's solved modes (the same thread owns row y at every call)
+      float m = rm[y];
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < nk) m = fmaxf(m, fmaxf(fabsf((float)re[q]), fabsf((float)im[q])));
+      rm[y] = m;
     }
     T* row = slice + (int64_t)y * 2 * sx + k0;
     if (VEC && nk == NB && sizeof(T) == 4 && NB % 4 == 0) {
@@ -421,7 +429,7 @@ template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B,
 __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                      const T* __restrict__ tup, const T* __restrict__ lu,
                                                      double lo, double up, int F, int sx, int sy, int ldy,
-                                                     int klo, int khi) {
+                                                     int klo, int khi, float* __restrict__ rmax) {
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
   using MF = SweepMfma<T>;
   constexpr int NCB = 2 * NB / 16;
@@ -463,6 +471,8 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
 
   const int n = blockIdx.x, b = blockIdx.y;
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
+  // a window's running row maxima of the solved modes (rows of this slice), or null
+  float* rm = rmax ? rmax + ((int64_t)b * F + n) * sy : nullptr;
   const T* tre = tup;
   const T* tim = tup + (int64_t)sx * sx;
   const double2 l2 = lam[F + n];
@@ -536,7 +546,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     T* nim = nre + NB * ldy;
     if (st > 0) {   // block kb+1, solved in the previous step, to global memory
       const int k0p = k0 + NB, nkp = min(NB, khi - k0p);
-      if constexpr (WIN) wsol_store<T, NB, R, VEC>(slice, wsol, k0p, nkp, sx, sy, P, tid, SWT);
+      if constexpr (WIN) wsol_store<T, NB, R, VEC>(slice, wsol, k0p, nkp, sx, sy, P, tid, SWT, rm);
       else if (VEC && nkp == NB) tile_store_vec<T, NB, R * P>(slice, nre, nim, k0p, sx, sy, ldy, R, tid, SWT);
       else tile_store_by(slice, nre, nim, k0p, nkp, NB, sx, sy, ldy, R, tid, SWT);
       // block kb's pivots, loaded by the coupling waves in the previous step
@@ -806,7 +816,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
   {  // the first block of the window, solved in the last step
     const int nkp = min(NB, khi - klo);
     if constexpr (WIN) {
-      wsol_store<T, NB, R, VEC>(slice, wsol, klo, nkp, sx, sy, P, (int)threadIdx.x, SWT);
+      wsol_store<T, NB, R, VEC>(slice, wsol, klo, nkp, sx, sy, P, (int)threadIdx.x, SWT, rm);
     } else {
       T* pre = tiles + ((nblk - 1) & 1) * TS;
       tile_store_by(slice, pre, pre + NB * ldy, klo, nkp, NB, sx, sy, ldy, R, (int)threadIdx.x, SWT);
@@ -1072,18 +1082,33 @@ __global__ __launch_bounds__(NT) void k_line_lu(T* __restrict__ lu, const double
 // B[k][n'] with n' < NW the real and n' >= NW the imaginary part of mode
 // klo + n' mod NW:  B^T = [[Tr, -Ti], [Ti, Tr]] restricted to those rows and to
 // the columns j >= khi of both halves (tfar holds the whole 2nx x 2nx B^T).
-// Operands in split bf16 (three parts each, the six products down to relative
-// size 2^-16, as in the x-transform), float32 accumulation.  Tiles of 128 rows
-// x 2 NW = 128 columns x 32, 2 x 2 waves of 64 x 64; the accumulators go
-// through LDS so that each thread can combine a mode's real and imaginary
-// parts and apply the complex lambda2 of its row's frequency.  Needs
-// nx % 32 == 0 (k chunks do not straddle the two halves; 16-byte loads).
+// Operands split on MFMA with float32 accumulation, in one of two forms:
+//  * F16 (the default): each W row scaled by the power of two that brings the
+//    largest of its solved modes (rmax, kept by the window kernels) into
+//    [2^13, 2^14), B^T by the power of two tscale (its largest entry into the
+//    same range), both split into fp16 hi + lo (22 significant bits), and the
+//    three products hi hi + hi lo + lo hi; the dropped lo lo term is 2^-22 of
+//    |W| |T|, below the rounding of a float32 dot product of the same length;
+//  * bf16: three parts each, the six products down to relative size 2^-16.
+// Tiles of 128 rows x 2 NW = 128 columns x 32, 2 x 2 waves of 64 x 64; the
+// accumulators go through LDS so that each thread can combine a mode's real
+// and imaginary parts and apply the complex lambda2 of its row's frequency.
+// Needs nx % 32 == 0 (k chunks do not straddle the two halves; 16-byte loads).
 constexpr int FAR_NW = 64;   // modes per column tile; a window takes SWEEP_WINDOW / 64 of them
 
+// Power of two bringing m into [2^13, 2^14) (1 for m = 0).
+__device__ __forceinline__ float far_rowscale(float m) {
+  int e = 0;
+  (void)frexpf(m, &e);   // m = f 2^e, f in [0.5, 1)
+  return m > 0.f ? ldexpf(1.f, 14 - e) : 1.f;
+}
+
+template <bool F16>
 __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, const unsigned short* __restrict__ Bt,
                                                   const double2* __restrict__ lam, int64_t rows, int F, int sx,
-                                                  int sy, int klo, int khi) {
-  constexpr int BM = 128, BN = 2 * FAR_NW, BK = 32, NA = 3;
+                                                  int sy, int klo, int khi, const float* __restrict__ rmax,
+                                                  float tinv) {
+  constexpr int BM = 128, BN = 2 * FAR_NW, BK = 32, NA = F16 ? 2 : 3;
   static_assert(BN == 128, "tile");
   auto off = [](int r, int ch) { return r * BK + 8 * (ch ^ ((r >> 1) & 3)); };
   constexpr int STAGE = 2 * NA * BM * BK;      // unsigned shorts of the A and B staging
@@ -1112,11 +1137,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
   uint4 rb[NA][2];
   int64_t arow[4];
   bool aok[4];
+  float rsc[4];   // F16: the staged rows' scales
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t gm = m0 + (tid >> 3) + 32 * i;
     aok[i] = gm < rows;
-    arow[i] = (aok[i] ? gm : rows - 1) * ld + 4 * (tid & 7);
+    const int64_t gc = aok[i] ? gm : rows - 1;
+    arow[i] = gc * ld + 4 * (tid & 7);
+    rsc[i] = F16 ? far_rowscale(rmax[gc]) : 1.f;
   }
   int64_t brow[2];
 #pragma unroll
@@ -1149,11 +1177,18 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
       us4 prt[NA];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        float rest = v[q];
+        if constexpr (F16) {   // exact power-of-two scale, then hi and the exact residual
+          const float x = v[q] * rsc[i];
+          const _Float16 h = (_Float16)x;
+          prt[0][q] = __builtin_bit_cast(unsigned short, h);
+          prt[1][q] = __builtin_bit_cast(unsigned short, (_Float16)(x - (float)h));
+        } else {
+          float rest = v[q];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          prt[a][q] = bf16_bits(rest);
-          if (a + 1 < NA) rest -= bf16_val(prt[a][q]);
+          for (int a = 0; a < NA; ++a) {
+            prt[a][q] = bf16_bits(rest);
+            if (a + 1 < NA) rest -= bf16_val(prt[a][q]);
+          }
         }
       }
 #pragma unroll
@@ -1186,12 +1221,21 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
       for (int x = 0; x < NA; ++x) a[x] = *reinterpret_cast<const bf8*>(&As[x * BM * BK + off(wm0 + 16 * i + lr, lk)]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc[i][j], 0, 0, 0);
+        if constexpr (F16) {   // small terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[1]), __builtin_bit_cast(h8, b[0][j]),
+                                                             acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[0]), __builtin_bit_cast(h8, b[1][j]),
+                                                             acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a[0]), __builtin_bit_cast(h8, b[0][j]),
+                                                             acc[i][j], 0, 0, 0);
+        } else {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[NA - 1], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[NA - 1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc[i][j], 0, 0, 0);
+        }
       }
     }
   };
@@ -1233,7 +1277,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
     static_assert(FAR_NW == 64, "thread -> (row, mode) map");
     constexpr int PER = 64 * FAR_NW / NT;
     const int q = tid & 63;
-    float yr[PER], yi[PER];
+    float yr[PER], yi[PER], rm[PER];
     double2 l2v[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
@@ -1241,12 +1285,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
       const int64_t gm = m0 + 64 * h + r;
       yr[t] = 0.f;
       yi[t] = 0.f;
+      rm[t] = 0.f;
       l2v[t] = double2{0.0, 0.0};
       if (gm < rows) {
         const float* src = spec + gm * ld + klo + q;
         yr[t] = src[0];
         yi[t] = src[sx];
         l2v[t] = lam[F + (int)((gm / sy) % F)];
+        if constexpr (F16) rm[t] = rmax[gm];
       }
     }
 #pragma unroll
@@ -1255,7 +1301,8 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
       const int64_t gm = m0 + 64 * h + r;
       if (gm < rows) {
         const float l2r = (float)l2v[t].x, l2i = (float)l2v[t].y;
-        const float cr = Cs[r * LDC + q], ci = Cs[r * LDC + FAR_NW + q];
+        const float us = F16 ? tinv / far_rowscale(rm[t]) : 1.f;   // undo the operand scales (powers of two)
+        const float cr = us * Cs[r * LDC + q], ci = us * Cs[r * LDC + FAR_NW + q];
         float* dst = spec + gm * ld + klo + q;
         dst[0] = yr[t] - (l2r * cr - l2i * ci);
         dst[sx] = yi[t] - (l2r * ci + l2i * cr);
@@ -1321,7 +1368,7 @@ void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int
                            : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B, false>);
   lds_limit((const void*)kfn, lds);
   kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
-                                       g.F, g.sx, g.sy, sh.ldy, klo, khi);
+                                       g.F, g.sx, g.sy, sh.ldy, klo, khi, win ? pl.d_rmax : nullptr);
 }
 
 // (NB, BK) of the wide kernel per precision and row count.
@@ -1403,6 +1450,15 @@ bool sweep_windowed(const Plan& pl) {
          g.sx >= 2 * SWEEP_WINDOW && g.sx % 32 == 0;
 }
 
+static __global__ __launch_bounds__(NT) void k_zero_f32(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+static void fill_zero_f32(float* p, int64_t n, hipStream_t s) {
+  k_zero_f32<<<(unsigned)((n + NT - 1) / NT), NT, 0, s>>>(p, n);
+}
+
 void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
   if (pl.prec == Prec::F64) {
     launch<double>(pl, op, (double*)spec, s);
@@ -1418,11 +1474,15 @@ void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
   const Geom& g = pl.g;
   const int64_t rows = (int64_t)g.B * g.F * g.sy;
   const unsigned tiles = (unsigned)((rows + 127) / 128);
+  // the rows' running maxima start from zero (a fill kernel: no memset node
+  // for callers that capture the sequence)
+  fill_zero_f32(pl.d_rmax, rows, s);
   for (int khi = g.sx; khi > 0; khi -= SWEEP_WINDOW) {
     const int klo = khi - SWEEP_WINDOW;
     if (khi < g.sx)
-      k_sweep_far<<<dim3(tiles, SWEEP_WINDOW / FAR_NW), NT, 0, s>>>((float*)spec, (const unsigned short*)op.tfar,
-                                                                   pl.d_lam, rows, g.F, g.sx, g.sy, klo, khi);
+      k_sweep_far<true><<<dim3(tiles, SWEEP_WINDOW / FAR_NW), NT, 0, s>>>(
+          (float*)spec, (const unsigned short*)op.tfar, pl.d_lam, rows, g.F, g.sx, g.sy, klo, khi, pl.d_rmax,
+          op.tfar_inv);
     launch<float>(pl, op, (float*)spec, s, klo, khi);
   }
 }
