@@ -37,6 +37,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short bf16_bits(float v) {
@@ -1129,12 +1130,13 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
   const int64_t ld = 2 * (int64_t)sx;          // row length of the buffer and of B^T
   const int64_t part = ld * ld;                // elements per bf16 part of B^T
 
-  // the W rows come from HBM once per tile: two k chunks of them in flight,
+  // the W rows come from HBM once per tile: DA k chunks of them in flight,
   // the B^T chunk (shared by every tile, from L2) one.  Rows beyond the
   // buffer load a valid row and are zeroed afterwards, so the loads carry no
   // branches and the waits can count them.
-  float4 ra[2][4];
-  uint4 rb[NA][2];
+  constexpr int DA = 2;   // A chunks in flight (a third spills)
+  float4 ra[DA][4];
+  u32x4 rb[NA][2];   // a native vector type: with HIP's uint4 struct this array went to scratch memory
   int64_t arow[4];
   bool aok[4];
   float rsc[4];   // F16: the staged rows' scales
@@ -1165,7 +1167,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int a = 0; a < NA; ++a) rb[a][i] = *reinterpret_cast<const uint4*>(Bt + a * part + brow[i] + k);
+      for (int a = 0; a < NA; ++a) rb[a][i] = *reinterpret_cast<const u32x4*>(Bt + a * part + brow[i] + k);
   };
   auto sstore = [&](auto bufc) {
     constexpr int bb = decltype(bufc)::value;
@@ -1198,7 +1200,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
     for (int i = 0; i < 2; ++i) {
       const int r = (tid >> 2) + 64 * i, c = 8 * (tid & 3);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&Bs[a * BN * BK + off(r, c >> 3)]) = rb[a][i];
+      for (int a = 0; a < NA; ++a) *reinterpret_cast<u32x4*>(&Bs[a * BN * BK + off(r, c >> 3)]) = rb[a][i];
     }
   };
 
@@ -1239,25 +1241,25 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
       }
     }
   };
+  // one k chunk: stage chunk k (A from buffer dc), issue the loads DA chunks
+  // ahead into the freed buffer and B one chunk ahead, multiply
+  auto step = [&](auto dc, int k) {
+    __syncthreads();
+    sstore(dc);
+    __syncthreads();
+    if (k + DA * BK < K2) aload(dc, k + DA * BK);
+    if (k + BK < K2) bload(k + BK);
+    compute();
+  };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
   aload(I0{}, 0);
   bload(0);
   if (BK < K2) aload(I1{}, BK);
-  for (int kk = 0; kk < K2; kk += 2 * BK) {
-    __syncthreads();
-    sstore(I0{});
-    __syncthreads();
-    if (kk + 2 * BK < K2) aload(I0{}, kk + 2 * BK);
-    if (kk + BK < K2) bload(kk + BK);
-    compute();
+  for (int kk = 0; kk < K2; kk += DA * BK) {
+    step(I0{}, kk);
     if (kk + BK >= K2) break;
-    __syncthreads();
-    sstore(I1{});
-    __syncthreads();
-    if (kk + 3 * BK < K2) aload(I1{}, kk + 3 * BK);
-    if (kk + 2 * BK < K2) bload(kk + 2 * BK);
-    compute();
+    step(I1{}, kk + BK);
   }
   // the accumulators through LDS (reusing the staging buffers), 64 rows at a
   // time: the two waves of row half h write, then every thread takes
