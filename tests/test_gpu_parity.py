@@ -95,9 +95,9 @@ def test_schur_sweep_shapes(nx, ny, prec):
     assert err < PREC_TOL[prec]
 
 
-# Windowed back-sweep (split bf16, x-sizes that are multiples of 64): the
-# coupling of each 64-mode window to the later ones is one product over all
-# slices before the window is swept.  Rows per line from 20 to 300 (1 .. 64
+# Windowed back-sweep (split-bf16 and split-fp16 modes, x-sizes that are
+# multiples of 64): the coupling of each 64-mode window to the later ones is
+# one row-scaled split-fp16 product over all slices before the window is swept.  Rows per line from 20 to 300 (1 .. 64
 # lanes; 150 and 256 rows give the coupling waves row ranges that are not a
 # multiple of their 32-row passes), two to four windows.  The error against
 # the oracle must stay at the float32 level of the same plan in plain float32
@@ -122,6 +122,30 @@ def test_windowed_sweep_shapes(nx, ny):
           f"split fp16 x-transform {errs['fp32_fp16gemm']:.3e}")
     assert errs["fp32_bf16gemm"] <= 4 * errs["fp32"] + 1e-6
     assert errs["fp32_fp16gemm"] <= 4 * errs["fp32"] + 1e-6
+
+
+# The far product's fp16 operands are scaled per row by the largest solved
+# mode of that row: a batch with a zero entry and entries scaled by 1e30 and
+# 1e-30 must give each entry's own result (linearity: c r -> c z), with no
+# overflow or flush to zero on the way.
+@pytest.mark.parametrize("prec", ["fp32_bf16gemm", "fp32_fp16gemm"])
+def test_windowed_sweep_scaled_batch(prec):
+    announce(f"windowed sweep scaled batch {prec}")
+    cfg = dict(dim=2, nx=128, ny=20, nt=8, scheme="tr", T=0.5, nu=0.05, ax=1.0, ay=0.5, alpha=1e-2)
+    r = np.random.default_rng(5).standard_normal((cfg["nt"], 128 * 20))
+    scales = [1.0, 0.0, 1e30, 1e-30]
+    torch, pd, prob = make(cfg, prec, batch=len(scales))
+    z_ref = o_prec.three_steps(prob, r)
+    rb = np.stack([c * r for c in scales])
+    z = pd.apply_precond(to_gpu(torch, rb, pd.shape)).cpu().numpy().reshape(len(scales), prob.nt, -1)
+    assert np.all(np.isfinite(z))
+    assert np.all(z[1] == 0.0)
+    for b, c in enumerate(scales):
+        if c == 0.0:
+            continue
+        err = rel_err(z[b] / c, z_ref)
+        print(f"  scale {c:g}: rel err {err:.3e}")
+        assert err < PREC_TOL[prec]
 
 
 # Sine-basis x-transform by FFT (nx + 1 a power of two: a DST-I as one complex
