@@ -546,8 +546,8 @@ DTYPE = {"fp32_bf16gemm": "f64 krylov + f32 fft/line solves + split-bf16 mfma x-
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
-              f"single-GPU in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library runs "
+              f"on a single GPU", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
