@@ -1281,21 +1281,20 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
     const int q = tid & 63;
     float yr[PER], yi[PER], rm[PER];
     double2 l2v[PER];
+    // branch-free: rows beyond the buffer read the last row (their results
+    // are not stored), so all the loads issue before the first wait; the
+    // row's frequency in 32-bit arithmetic (the buffer has far fewer than
+    // 2^32 rows)
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
       const int r = (tid >> 6) + 4 * t;
       const int64_t gm = m0 + 64 * h + r;
-      yr[t] = 0.f;
-      yi[t] = 0.f;
-      rm[t] = 0.f;
-      l2v[t] = double2{0.0, 0.0};
-      if (gm < rows) {
-        const float* src = spec + gm * ld + klo + q;
-        yr[t] = src[0];
-        yi[t] = src[sx];
-        l2v[t] = lam[F + (int)((gm / sy) % F)];
-        if constexpr (F16) rm[t] = rmax[gm];
-      }
+      const int64_t gc = gm < rows ? gm : rows - 1;
+      const float* src = spec + gc * ld + klo + q;
+      yr[t] = src[0];
+      yi[t] = src[sx];
+      l2v[t] = lam[F + (int)(((unsigned)gc / (unsigned)sy) % (unsigned)F)];
+      rm[t] = F16 ? rmax[gc] : 0.f;
     }
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
