@@ -39,6 +39,10 @@ CASES = {
     "2d-be-schur-64": dict(dim=2, nx=64, ny=64, nt=32, scheme="be", T=1.0, nu=1e-2, ax=1.0, ay=0.5, alpha=1e-3),
     "2d-tr-schur-mid": dict(dim=2, nx=72, ny=150, nt=8, scheme="tr", T=0.5, nu=1e-2, ax=1.0, ay=-0.5, alpha=1e-3),
     "2d-tr-schur-tall": dict(dim=2, nx=40, ny=300, nt=8, scheme="tr", T=0.5, nu=2e-2, ax=1.0, ay=0.5, alpha=1e-2),
+    # x-transform products with K = N = 160 (a multiple of 32, so the split MFMA
+    # kernels run) and a ragged last column tile (160 = 128 + 32), 9 x 23 = 207
+    # rows (a ragged last row tile)
+    "2d-tr-schur-80": dict(dim=2, nx=80, ny=23, nt=16, scheme="tr", T=0.5, nu=2e-2, ax=1.0, ay=-0.4, alpha=1e-2),
 }
 
 PREC_TOL = {"fp64": 1e-11, "fp32": 2e-3, "fp32_bf16gemm": 2e-3, "fp32_bf16x1": 5e-2, "fp32_fp16gemm": 2e-3}
