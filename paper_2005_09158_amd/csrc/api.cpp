@@ -1053,6 +1053,9 @@ void paradiag_destroy(paradiag_plan plan) {
   if (!pl) return;
   for (auto& r : pl->timer.pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
   for (auto e : pl->timer.pool) hipEventDestroy(e);
+  if (pl->sweep_fork) hipEventDestroy(pl->sweep_fork);
+  if (pl->sweep_join) hipEventDestroy(pl->sweep_join);
+  if (pl->sweep_side) hipStreamDestroy(pl->sweep_side);
   if (pl->pin) hipHostFree(pl->pin);
   delete pl;
 }
@@ -1100,6 +1103,14 @@ paradiag_status paradiag_bind_workspace(paradiag_plan plan, void* workspace, siz
   if (pl->prec == Prec::F16 && pl->p.dim == 2)
     pl->d_rowscale = (float*)take(sizeof(float) * 2 * (size_t)g.B * g.F * g.sy);
   if (sweep_windowed(*pl)) pl->d_rmax = (float*)take(sizeof(float) * (size_t)g.B * g.F * g.sy);
+  if (sweep_windowed(*pl) && g.B >= 2 && !pl->sweep_side) {
+    if (hipStreamCreateWithFlags(&pl->sweep_side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->sweep_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->sweep_join, hipEventDisableTiming) != hipSuccess) {
+      set_error("creating the back-sweep's second stream");
+      return PD_ERR_HIP;
+    }
+  }
   up(pl->d_gam, pl->gam.data(), sizeof(double) * g.nt);
   up(pl->d_invgam, pl->invgam.data(), sizeof(double) * g.nt);
   {

@@ -139,6 +139,11 @@ struct Plan {
   void* d_dtw = nullptr;  // exp(-2 pi i k / (2 (nx + 1))), k < nx + 1, compute precision
   float* d_rowscale = nullptr;  // PD_PREC_FP32_FP16GEMM: power-of-two scale of every x-transform row
   float* d_rmax = nullptr;      // windowed back-sweep: running maximum of every spectral row's solved modes
+  // windowed back-sweep with a batch of two or more: the second half of the
+  // batch runs on a stream of its own (default priority), forked from and
+  // joined to the caller's stream by events
+  hipStream_t sweep_side = nullptr;
+  hipEvent_t sweep_fork = nullptr, sweep_join = nullptr;
   int L = 2;              // bands of the time stencil
   double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
   double theta = 1.0;

@@ -430,7 +430,7 @@ template <typename T, int R, int P, int NB, int RB, bool VEC, int MINB, int W0B,
 __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec, const double2* __restrict__ lam,
                                                      const T* __restrict__ tup, const T* __restrict__ lu,
                                                      double lo, double up, int F, int sx, int sy, int ldy,
-                                                     int klo, int khi, float* __restrict__ rmax) {
+                                                     int klo, int khi, float* __restrict__ rmax, int b0) {
   static_assert((2 * NB) % 16 == 0, "MFMA column blocks");
   using MF = SweepMfma<T>;
   constexpr int NCB = 2 * NB / 16;
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(SWT, MINB) void k_schur_sweep(T* __restrict__ spec,
     }
   };
 
-  const int n = blockIdx.x, b = blockIdx.y;
+  const int n = blockIdx.x, b = blockIdx.y + b0;   // right-hand sides b0 .. b0 + gridDim.y - 1
   T* slice = spec + ((int64_t)b * F + n) * sy * 2 * sx;
   // a window's running row maxima of the solved modes (rows of this slice), or null
   float* rm = rmax ? rmax + ((int64_t)b * F + n) * sy : nullptr;
@@ -1108,7 +1108,7 @@ template <bool F16>
 __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, const unsigned short* __restrict__ Bt,
                                                   const double2* __restrict__ lam, int64_t rows, int F, int sx,
                                                   int sy, int klo, int khi, const float* __restrict__ rmax,
-                                                  float tinv) {
+                                                  float tinv, int64_t r0) {
   constexpr int BM = 128, BN = 2 * FAR_NW, BK = 32, NA = F16 ? 2 : 3;
   static_assert(BN == 128, "tile");
   auto off = [](int r, int ch) { return r * BK + 8 * (ch ^ ((r >> 1) & 3)); };
@@ -1120,7 +1120,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep_far(float* __restrict__ spec, c
   unsigned short* Bs = As + NA * BM * BK;
   float* Cs = smem;
 
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int64_t m0 = r0 + (int64_t)blockIdx.x * BM;   // rows r0 .. rows - 1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
@@ -1352,7 +1352,7 @@ size_t piped_lds(const SweepShape& sh, bool win) {
 }
 
 template <typename T, int R, int P, int NB, int RB, int W0B>
-void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo, int khi) {
+void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo, int khi, int b0, int nb) {
   const Geom& g = pl.g;
   SweepShape sh = sweep_shape<T, NB, 16>(pl);
   const bool win = khi - klo < g.sx;
@@ -1368,8 +1368,8 @@ void launch_piped(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int
                     : (win ? k_schur_sweep<T, R, P, NB, RB, false, 2, W0B, true>
                            : k_schur_sweep<T, R, P, NB, RB, false, MINB, W0B, false>);
   lds_limit((const void*)kfn, lds);
-  kfn<<<dim3(g.F, g.B), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
-                                       g.F, g.sx, g.sy, sh.ldy, klo, khi, win ? pl.d_rmax : nullptr);
+  kfn<<<dim3(g.F, nb), SWT, lds, s>>>(spec, pl.d_lam, (const T*)op.tup, (const T*)op.lu, op.lo, op.up,
+                                      g.F, g.sx, g.sy, sh.ldy, klo, khi, win ? pl.d_rmax : nullptr, b0);
 }
 
 // (NB, BK) of the wide kernel per precision and row count.
@@ -1388,18 +1388,20 @@ template <> struct PipedCfg<double> { static constexpr int NB4 = 0, NB8 = 0; };
 // MFMA rate) is the long pole, and there all four waves run it.
 
 template <typename T>
-void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo = 0, int khi = -1) {
+void launch(const Plan& pl, const SpaceOp& op, T* spec, hipStream_t s, int klo = 0, int khi = -1, int b0 = 0,
+            int nb = -1) {
   using C = SweepCfg<T>;
   using PC = PipedCfg<T>;
   SweepShape sh = sweep_shape<T, C::NB, C::BK>(pl);
   if (khi < 0) khi = pl.g.sx;
+  if (nb < 0) nb = pl.g.B;
   if constexpr (PC::NB8 > 0) {   // float32: pipelined kernel
     // row blocks of 16 rows: W0 for wave 0 (after its lines), RB per coupling
     // wave, W0 + 3 RB >= rows / 16: <= 64 rows: 0 + 3 x 2, <= 128: 0 + 3 x 3,
     // <= 256: 1 + 3 x 5, <= 512: 2 + 3 x 10
 #define PD_PIPED(RR, PP, BB, W0, NBV)                                                     \
   if (sh.R == RR && sh.P == PP) {                                                         \
-    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s, klo, khi);                      \
+    launch_piped<T, RR, PP, NBV, BB, W0>(pl, op, spec, s, klo, khi, b0, nb);              \
     return;                                                                               \
   }
     PD_PIPED(4, 1, 2, 0, PC::NB4) PD_PIPED(4, 2, 2, 0, PC::NB4) PD_PIPED(4, 4, 2, 0, PC::NB4)
@@ -1474,17 +1476,40 @@ void schur_sweep(const Plan& pl, const SpaceOp& op, void* spec, hipStream_t s) {
   // the window's modes
   const Geom& g = pl.g;
   const int64_t rows = (int64_t)g.B * g.F * g.sy;
-  const unsigned tiles = (unsigned)((rows + 127) / 128);
   // the rows' running maxima start from zero (a fill kernel: no memset node
   // for callers that capture the sequence)
   fill_zero_f32(pl.d_rmax, rows, s);
+  // The sweep is independent per slice.  With a batch of two or more, the
+  // second half of the right-hand sides runs on the plan's second stream, so
+  // that one half's far products (HBM-bound) and the last round of its window
+  // launches overlap the other half's window launches (bound by the serial
+  // line solves).
+  const bool two = pl.sweep_side != nullptr && g.B >= 2;
+  const int bh = two ? g.B / 2 : g.B;
+  const int64_t rh = (int64_t)bh * g.F * g.sy;   // first row of the second half
+  hipStream_t s2 = two ? pl.sweep_side : s;
+  if (two) {
+    hipEventRecord(pl.sweep_fork, s);
+    hipStreamWaitEvent(s2, pl.sweep_fork, 0);
+  }
+  auto far = [&](hipStream_t st, int64_t ra, int64_t rb, int klo, int khi) {
+    const unsigned tiles = (unsigned)((rb - ra + 127) / 128);
+    k_sweep_far<true><<<dim3(tiles, SWEEP_WINDOW / FAR_NW), NT, 0, st>>>(
+        (float*)spec, (const unsigned short*)op.tfar, pl.d_lam, rb, g.F, g.sx, g.sy, klo, khi, pl.d_rmax,
+        op.tfar_inv, ra);
+  };
   for (int khi = g.sx; khi > 0; khi -= SWEEP_WINDOW) {
     const int klo = khi - SWEEP_WINDOW;
-    if (khi < g.sx)
-      k_sweep_far<true><<<dim3(tiles, SWEEP_WINDOW / FAR_NW), NT, 0, s>>>(
-          (float*)spec, (const unsigned short*)op.tfar, pl.d_lam, rows, g.F, g.sx, g.sy, klo, khi, pl.d_rmax,
-          op.tfar_inv);
-    launch<float>(pl, op, (float*)spec, s, klo, khi);
+    if (khi < g.sx) far(s, 0, rh, klo, khi);
+    launch<float>(pl, op, (float*)spec, s, klo, khi, 0, bh);
+    if (two) {
+      if (khi < g.sx) far(s2, rh, rows, klo, khi);
+      launch<float>(pl, op, (float*)spec, s2, klo, khi, bh, g.B - bh);
+    }
+  }
+  if (two) {
+    hipEventRecord(pl.sweep_join, s2);
+    hipStreamWaitEvent(s, pl.sweep_join, 0);
   }
 }
 

@@ -131,13 +131,14 @@ def test_windowed_sweep_shapes(nx, ny):
 # The far product's fp16 operands are scaled per row by the largest solved
 # mode of that row: a batch with a zero entry and entries scaled by 1e30 and
 # 1e-30 must give each entry's own result (linearity: c r -> c z), with no
-# overflow or flush to zero on the way.
+# overflow or flush to zero on the way.  Five entries: the sweep runs the
+# first two and the last three on two streams.
 @pytest.mark.parametrize("prec", ["fp32_bf16gemm", "fp32_fp16gemm"])
 def test_windowed_sweep_scaled_batch(prec):
     announce(f"windowed sweep scaled batch {prec}")
     cfg = dict(dim=2, nx=128, ny=20, nt=8, scheme="tr", T=0.5, nu=0.05, ax=1.0, ay=0.5, alpha=1e-2)
     r = np.random.default_rng(5).standard_normal((cfg["nt"], 128 * 20))
-    scales = [1.0, 0.0, 1e30, 1e-30]
+    scales = [1.0, 0.0, 1e30, 1e-30, -2.5]
     torch, pd, prob = make(cfg, prec, batch=len(scales))
     z_ref = o_prec.three_steps(prob, r)
     rb = np.stack([c * r for c in scales])
