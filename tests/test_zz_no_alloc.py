@@ -22,6 +22,8 @@ pytestmark = pytest.mark.gpu
 CASES = [
     # (problem, precision, batch): larger first, then smaller
     (dict(dim=2, nx=40, ny=36, nt=32, scheme="tr", T=1.0, nu=2e-2, ax=1.0, ay=0.5, alpha=1e-3), "fp64", 3),
+    # windowed back-sweep (two 64-mode windows) over two streams
+    (dict(dim=2, nx=128, ny=20, nt=8, scheme="tr", T=0.5, nu=0.05, ax=1.0, ay=0.5, alpha=1e-2), "fp32_bf16gemm", 2),
     (dict(dim=2, nx=17, ny=9, nt=8, scheme="lf", T=1.0, nu=1.0, alpha=1e-2), "fp32_bf16gemm", 1),
 ]
 
